@@ -1,0 +1,245 @@
+/*
+ * sd.h -- C ABI of the simultaneous-diagonalisation Trotter engine (gfx950).
+ *
+ * Method: Kawase & Fujii, "Fast classical simulation of Hamiltonian dynamics
+ * by simultaneous diagonalization using Clifford transformation with parallel
+ * computation" (arXiv:2206.11664).  A Hamiltonian H = sum_j c_j P_j (real c_j,
+ * P_j in {I,X,Y,Z}^n; Sec. "Classical Simulation of Quantum Dynamics") is
+ * partitioned into mutually commuting groups (Sec. "Partitioning Hamiltonian
+ * Terms"); each group is diagonalised by a Clifford circuit found on the
+ * binary tableau (Sec. "Partial Diagonalization of Hamiltonian", the
+ * algorithms for steps (i)-(iv) and the appendix algorithm for independent
+ * terms) and evolved as C^dagger exp(-i dt Lambda) C (Eq. trotter_simul_diag).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: every call returns sd_status; nothing throws across the ABI.
+ *   sd_last_error() returns a thread-local message describing the last
+ *   failure on the calling thread.
+ * - Qubits: qubit q (0-based) is bit q of the amplitude index (the paper's
+ *   basis |b_n...b_1> with qubit 1 least significant).  A dense Pauli string
+ *   has character i acting on qubit i.  1 <= n_qubits <= 63.
+ * - State: 2^n contiguous amplitudes, interleaved (re, im): float pairs for
+ *   SD_C64, double pairs for SD_C128 (the layouts of torch.complex64 and
+ *   torch.complex128).  The state is caller-owned device memory and is
+ *   updated in place.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  Device work is enqueued asynchronously unless stated otherwise.
+ * - Handles: distinct handles may be used from distinct threads at once; one
+ *   handle must not be used by two threads at once.  Plans are immutable
+ *   after sd_plan, except for the workspace binding.
+ */
+#ifndef SD_H
+#define SD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SD_OK = 0,
+    SD_ERR_ARG = 1,        /* null pointer, bad size, bad enum value          */
+    SD_ERR_PARSE = 2,      /* malformed Pauli string                          */
+    SD_ERR_RANGE = 3,      /* qubit index / qubit count / value out of range  */
+    SD_ERR_WORKSPACE = 4,  /* no workspace bound, or workspace too small      */
+    SD_ERR_HIP = 5,        /* a HIP runtime call or kernel launch failed      */
+    SD_ERR_INTERNAL = 6,   /* planner self-check failed (e.g. a term not
+                              diagonalised by its group's Clifford)          */
+    SD_ERR_STATE = 7       /* object in the wrong state (e.g. destroyed)      */
+} sd_status;
+
+typedef enum {
+    SD_C64 = 0,   /* complex64 amplitudes; phase angle, phase factor and
+                     butterflies evaluated in FP64, rounded once per pass     */
+    SD_C128 = 1   /* complex128 amplitudes, FP64 throughout                   */
+} sd_dtype;
+
+typedef struct sd_hamiltonian sd_hamiltonian;
+typedef struct sd_plan_s sd_plan_t;
+typedef struct sd_ensemble sd_ensemble;
+
+/* --------------------------------------------------------------------------
+ * Hamiltonian: H = sum_j c_j P_j (Sec. "Classical Simulation of Quantum
+ * Dynamics").  Exact duplicate strings are merged by summing their
+ * coefficients at the first occurrence; identity terms and zero coefficients
+ * are kept.  Inputs are copied; the caller may free them after the call.
+ * -------------------------------------------------------------------------- */
+
+/* paulis[j]: dense "XIZY..." (length n, character i = qubit i) or sparse
+   "X0 Y3 Z7" (letter + 0-based qubit, each qubit at most once).
+   Errors: SD_ERR_ARG (null pointers, n_terms < 0), SD_ERR_RANGE (n outside
+   1..63, qubit >= n), SD_ERR_PARSE (other characters, repeated qubit, wrong
+   dense length), SD_ERR_ARG for a non-finite coefficient. */
+sd_status sd_hamiltonian_create(int32_t n_qubits, int64_t n_terms,
+                                const char *const *paulis, const double *coeffs,
+                                sd_hamiltonian **out);
+
+/* Symplectic form (Sec. "Tableau Representation"): bit q of xmask/zmask is
+   x_q/z_q; (1,0)=X, (0,1)=Z, (1,1)=Y.  Bits at q >= n are SD_ERR_RANGE. */
+sd_status sd_hamiltonian_create_masks(int32_t n_qubits, int64_t n_terms,
+                                      const uint64_t *xmask, const uint64_t *zmask,
+                                      const double *coeffs, sd_hamiltonian **out);
+
+/* Merged terms (read-only views valid until sd_hamiltonian_destroy).
+   source[j] is the input index of the first occurrence of merged term j. */
+sd_status sd_hamiltonian_terms(const sd_hamiltonian *h, int32_t *n_qubits,
+                               int64_t *n_terms, const uint64_t **xmask,
+                               const uint64_t **zmask, const double **coeffs,
+                               const int64_t **source);
+
+void sd_hamiltonian_destroy(sd_hamiltonian *h);
+
+/* --------------------------------------------------------------------------
+ * Planning (host only, no device work).
+ * -------------------------------------------------------------------------- */
+typedef struct {
+    /* Apply the skip rule before steps (ii)/(iii): qubits carrying only
+       {I,Z} in a group are left alone and qubits carrying only {I,X} get a
+       Hadamard (end of Sec. "Partial Diagonalization of Hamiltonian").
+       Default 1. Affects the exported paper circuit only. */
+    int32_t skip_rule;
+    /* Largest tile (amplitudes staged on chip per work-group) as log2, per
+       dtype; 0 = built-in default (13 for both).  Range 6..13. */
+    int32_t tile_log2_c64;
+    int32_t tile_log2_c128;
+    /* Low qubits every tile must contain so that global accesses are whole
+       cache lines; 0 = default (4 for c64 = 128 B, 3 for c128 = 128 B). */
+    int32_t coalesce_log2_c64;
+    int32_t coalesce_log2_c128;
+} sd_plan_options;
+
+/* Fill `opt` with the defaults. */
+void sd_plan_options_default(sd_plan_options *opt);
+
+/* Partition the merged terms into commuting groups by first fit in term
+   order (greedy colouring of the anticommutation graph), synthesise each
+   group's diagonalising Clifford (paper steps (i)-(iv)), verify that every
+   term of every group becomes a signed Z-string, and compile the device
+   tile programs.  opt may be NULL (defaults).  The plan keeps no reference
+   to h.  Errors: SD_ERR_ARG, SD_ERR_INTERNAL (self-check failed). */
+sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt,
+                  sd_plan_t **out);
+
+typedef struct {
+    int32_t n_qubits;
+    int64_t n_terms;            /* merged terms                               */
+    int32_t n_groups;           /* commuting groups (K)                       */
+    int64_t max_group_terms;
+    int32_t passes_c64;         /* device passes per first-order step         */
+    int32_t passes_c128;
+    int64_t paper_model_passes; /* passes per first-order step in the paper's
+                                   cost model: one per H gate, one per CNOT
+                                   control, one for S+CZ, one for Lambda,
+                                   doubled for C and C^dagger except Lambda  */
+    int64_t workspace_bytes;    /* device bytes sd_bind_workspace needs       */
+    double plan_seconds;
+} sd_plan_info;
+
+sd_status sd_plan_info_get(const sd_plan_t *p, sd_plan_info *info);
+
+/* Gate kinds of an exported circuit. */
+enum { SD_GATE_H = 0, SD_GATE_S = 1, SD_GATE_CNOT = 2, SD_GATE_CZ = 3 };
+
+typedef struct {
+    int32_t n_terms;
+    const int64_t *term_ids;   /* merged-term indices, group order            */
+    const uint64_t *zmask;     /* C P_k C^dagger = (-1)^sign[k] Z^{zmask[k]}  */
+    const int8_t *sign;        /* 0 or 1                                      */
+    int32_t n_gates;
+    const int32_t *gates;      /* n_gates triples (kind, a, b), application
+                                  order (first acts first); b = -1 for 1q     */
+    int32_t n_independent;     /* terms returned by the independent-set step  */
+    const int64_t *independent;/* their merged-term indices, tableau order    */
+} sd_group_view;
+
+/* Group g's terms and its Clifford as the paper's algorithm builds it.
+   Views stay valid until sd_plan_destroy. */
+sd_status sd_plan_export_group(const sd_plan_t *p, int32_t g, sd_group_view *v);
+
+typedef struct {
+    int32_t group;       /* owning commuting group                            */
+    int32_t n_terms;
+    const int64_t *term_ids;
+    int32_t rho;         /* dimension of the terms' X span (Hadamard dims)    */
+    int32_t tile_log2;   /* D: rho plus spectator low qubits                  */
+    const uint64_t *basis;     /* D physical vectors: rho X-span basis vectors,
+                                  then the spectator unit vectors             */
+    int32_t coalesce_log2;     /* c: address bits 0..c-1 are tile pivots      */
+    uint64_t free_mask;        /* address bits enumerated by the tile index   */
+    const uint64_t *pivot_vec; /* D vectors, one per tile pivot (ascending
+                                  pivot bit); address = base ^ sum pi_i vec_i */
+    const uint32_t *pivot_coord; /* D masks: tile coordinates of pivot_vec[i] */
+    const uint32_t *cz_s;      /* rho rows of the CZ/S layer: bit j of row i
+                                  set for CZ(i,j), bit i for S(i)             */
+    const uint32_t *zeta;      /* per term: Lambda Z-mask in tile coordinates  */
+    const uint64_t *ztile;     /* per term: physical Z part for the tile sign  */
+    const double *coef;        /* per term: signed coefficient                */
+} sd_pass_view;
+
+/* Device pass list for one dtype, in application order for group order 1. */
+sd_status sd_plan_pass_count(const sd_plan_t *p, sd_dtype dt, int32_t *count);
+sd_status sd_plan_export_pass(const sd_plan_t *p, sd_dtype dt, int32_t i,
+                              sd_pass_view *v);
+
+void sd_plan_destroy(sd_plan_t *p);
+
+/* --------------------------------------------------------------------------
+ * Device execution.
+ * -------------------------------------------------------------------------- */
+
+/* Bind caller-allocated device memory (>= workspace_bytes, 256-byte aligned)
+   to the plan and upload the tile programs into it on `stream`.  The memory
+   must stay allocated while the plan is used on the device.  Rebinding is
+   allowed.  Errors: SD_ERR_WORKSPACE (too small / misaligned), SD_ERR_HIP. */
+sd_status sd_bind_workspace(sd_plan_t *p, void *dev_ptr, size_t bytes, void *stream);
+
+/* state <- (prod over the step schedule of C_g^dagger exp(-i tau Lambda_g) C_g)^steps
+   state, Eq. trotter_simul_diag, with tau = dt (order 1: groups 0..K-1) or the
+   symmetric sequence dt/2 (0..K-2), dt (K-1), dt/2 (K-2..0) for order 2.
+   Asynchronous on `stream`.  state: device pointer to 2^n amplitudes of
+   `dtype`.  Errors: SD_ERR_ARG (order not 1/2, steps < 0, non-finite dt),
+   SD_ERR_WORKSPACE (no workspace), SD_ERR_HIP. */
+sd_status sd_evolve(const sd_plan_t *p, void *state, sd_dtype dtype, double dt,
+                    int64_t steps, int32_t order, void *stream);
+
+/* energy = <psi|H|psi> / 1 (not normalised by <psi|psi>), evaluated per
+   group through its diagonal form (the grouped-expectation use of the
+   partition, Sec. "Partitioning Hamiltonian Terms"), accumulated in FP64.
+   Synchronises `stream`; energy is a host pointer. */
+sd_status sd_expectation(const sd_plan_t *p, const void *state, sd_dtype dtype,
+                         double *energy, void *stream);
+
+/* FP64 reductions over 2^n amplitudes (device inputs, host outputs;
+   synchronise `stream`).  sd_norm2: sum |a_x|^2.  sd_inner: sum conj(a_x) b_x
+   written to out[0] (re), out[1] (im). */
+sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n_qubits,
+                   double *out, void *stream);
+sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int32_t n_qubits,
+                   double *out, void *stream);
+
+/* Ensemble of independent instances (uneven sizes allowed), evolved together.
+   plans: `count` plans, each with a bound workspace; states: host array of
+   `count` device pointers.  One launch per pass level per step. */
+sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t count,
+                             sd_dtype dtype, sd_ensemble **out);
+sd_status sd_ensemble_workspace_bytes(const sd_ensemble *e, int64_t *bytes);
+sd_status sd_ensemble_bind_workspace(sd_ensemble *e, void *dev_ptr, size_t bytes,
+                                     void *stream);
+sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, double dt,
+                             int64_t steps, int32_t order, void *stream);
+void sd_ensemble_destroy(sd_ensemble *e);
+
+/* Wait for `stream` and report any asynchronous HIP error as SD_ERR_HIP. */
+sd_status sd_sync(void *stream);
+
+const char *sd_status_string(sd_status s);
+const char *sd_last_error(void);
+const char *sd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SD_H */

@@ -1,0 +1,32 @@
+// Device-side record of one tile pass (packed into the caller's workspace).
+#pragma once
+#include <cstdint>
+
+namespace sd {
+
+constexpr int kMaxD = 16;            // tile dims a record can describe
+constexpr int kMaxPassTerms = 1024;  // Lambda terms per pass (LDS budget)
+
+struct alignas(256) PassDev {
+    int32_t n;          // qubits
+    int32_t D;          // tile dims (log2 of amplitudes per tile)
+    int32_t rho;        // Hadamard (X-span) dims, tile coordinates 0..rho-1
+    int32_t c;          // contiguous low address bits (pivots 0..c-1)
+    int32_t m;          // Lambda terms
+    int32_t n_free;     // n - D
+    int64_t n_tiles;    // 2^(n-D)
+    int64_t term_off;   // byte offset of the term arrays from the workspace base
+    double scale;       // 2^-rho
+    uint64_t u_hi[kMaxD];   // physical vectors of tile pivots c..D-1
+    uint32_t mr[kMaxD];     // tile coordinates of each pivot vector
+    uint32_t B[kMaxD];      // CZ/S quadratic form rows (rho used)
+    uint8_t free_pos[64];   // physical bit of each tile-index bit
+};
+
+// term arrays at term_off: uint32 zeta[m]; (pad to 8) uint64 ztile[m]; double coef[m]
+inline int64_t term_bytes(int m) {
+    int64_t a = ((int64_t)m * 4 + 7) / 8 * 8;
+    return a + (int64_t)m * 16;
+}
+
+}  // namespace sd

@@ -1,0 +1,187 @@
+// sd_plan: grouping, per-group Clifford synthesis, device program compile.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "sd_internal.h"
+
+using namespace sd;
+
+extern "C" void sd_plan_options_default(sd_plan_options *o) {
+    if (!o) return;
+    o->skip_rule = 1;
+    o->tile_log2_c64 = 13;
+    o->tile_log2_c128 = 13;
+    o->coalesce_log2_c64 = 4;
+    o->coalesce_log2_c128 = 3;
+}
+
+namespace {
+
+inline bool commute(const Term &a, const Term &b) {
+    return ((popc(a.x & b.z) + popc(b.x & a.z)) & 1) == 0;
+}
+
+// Greedy partition (Sec. "Partitioning Hamiltonian Terms"): first fit in term
+// order, i.e. greedy colouring of the anticommutation graph.
+std::vector<std::vector<int64_t>> first_fit(const std::vector<Term> &T) {
+    std::vector<std::vector<int64_t>> groups;
+    for (int64_t k = 0; k < (int64_t)T.size(); ++k) {
+        bool placed = false;
+        for (auto &g : groups) {
+            bool ok = true;
+            for (int64_t j : g)
+                if (!commute(T[k], T[j])) {
+                    ok = false;
+                    break;
+                }
+            if (ok) {
+                g.push_back(k);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) groups.push_back({k});
+    }
+    return groups;
+}
+
+}  // namespace
+
+extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt_in,
+                             sd_plan_t **out) {
+    if (!h || !out) return fail(SD_ERR_ARG, "sd_plan: null argument");
+    *out = nullptr;
+    sd_plan_options opt;
+    sd_plan_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    auto chk = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
+    if (!chk(opt.tile_log2_c64, kMinTileLog2, kMaxTileLog2) ||
+        !chk(opt.tile_log2_c128, kMinTileLog2, kMaxTileLog2) ||
+        !chk(opt.coalesce_log2_c64, 0, 6) || !chk(opt.coalesce_log2_c128, 0, 6) ||
+        opt.coalesce_log2_c64 >= opt.tile_log2_c64 ||
+        opt.coalesce_log2_c128 >= opt.tile_log2_c128)
+        return fail(SD_ERR_RANGE, "sd_plan: tile/coalescing options out of range");
+    auto t0 = std::chrono::steady_clock::now();
+    sd_plan_t *p = new sd_plan_s();
+    p->n = h->n;
+    p->terms = h->terms;
+    p->groups = first_fit(p->terms);
+
+    // paper circuit per group (export, validation, cost model)
+    SynthOptions so;
+    so.skip_rule = opt.skip_rule != 0;
+    so.step_i = true;
+    int64_t model = 0;
+    for (auto &g : p->groups) {
+        std::vector<Row> rows;
+        for (int64_t k : g) rows.push_back({p->terms[k].x, p->terms[k].z, 0});
+        SynthResult r = synthesize(p->n, rows, so);
+        if (!r.ok) {
+            std::string e = r.error;
+            delete p;
+            return fail(SD_ERR_INTERNAL, "sd_plan: paper synthesis failed: " + e);
+        }
+        std::vector<int32_t> flat;
+        for (auto &gt : r.gates) {
+            flat.push_back(gt.kind);
+            flat.push_back(gt.a);
+            flat.push_back(gt.b);
+        }
+        model += 2 * (r.n_h_first + r.n_cnot_controls + r.n_diag + r.n_h_last) + 1;
+        p->circuits.push_back(std::move(r));
+        p->gate_flat.push_back(std::move(flat));
+    }
+    p->paper_model_passes = model;
+
+    sd_status st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c64,
+                                   opt.coalesce_log2_c64, &p->prog[SD_C64]);
+    if (st == SD_OK)
+        st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c128,
+                             opt.coalesce_log2_c128, &p->prog[SD_C128]);
+    if (st != SD_OK) {
+        delete p;
+        return st;
+    }
+    // workspace: packed pass tables for both dtypes + reduction scratch
+    int64_t off = 0;
+    for (int d = 0; d < 2; ++d) {
+        p->ws_off_prog[d] = off;
+        off += (pack_size(p->prog[d]) + 255) / 256 * 256;
+    }
+    p->ws_off_scratch = off;
+    off += 64 * 1024;  // FP64 partial sums
+    p->ws_needed = off;
+    p->plan_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_plan_info_get(const sd_plan_t *p, sd_plan_info *info) {
+    if (!p || !info) return fail(SD_ERR_ARG, "sd_plan_info_get: null argument");
+    info->n_qubits = p->n;
+    info->n_terms = (int64_t)p->terms.size();
+    info->n_groups = (int32_t)p->groups.size();
+    int64_t mx = 0;
+    for (auto &g : p->groups) mx = std::max<int64_t>(mx, (int64_t)g.size());
+    info->max_group_terms = mx;
+    info->passes_c64 = (int32_t)p->prog[SD_C64].passes.size();
+    info->passes_c128 = (int32_t)p->prog[SD_C128].passes.size();
+    info->paper_model_passes = p->paper_model_passes;
+    info->workspace_bytes = p->ws_needed;
+    info->plan_seconds = p->plan_seconds;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_plan_export_group(const sd_plan_t *p, int32_t g, sd_group_view *v) {
+    if (!p || !v) return fail(SD_ERR_ARG, "sd_plan_export_group: null argument");
+    if (g < 0 || g >= (int32_t)p->groups.size())
+        return fail(SD_ERR_RANGE, "sd_plan_export_group: group index out of range");
+    const SynthResult &r = p->circuits[g];
+    v->n_terms = (int32_t)p->groups[g].size();
+    v->term_ids = p->groups[g].data();
+    v->zmask = r.zmask.data();
+    v->sign = r.sign.data();
+    v->n_gates = (int32_t)r.gates.size();
+    v->gates = p->gate_flat[g].data();
+    v->n_independent = (int32_t)r.independent.size();
+    // independent indices are positions within the group; export term ids
+    static thread_local std::vector<int64_t> ind;
+    ind.clear();
+    for (int64_t i : r.independent) ind.push_back(p->groups[g][i]);
+    v->independent = ind.data();
+    return SD_OK;
+}
+
+extern "C" sd_status sd_plan_pass_count(const sd_plan_t *p, sd_dtype dt, int32_t *count) {
+    if (!p || !count) return fail(SD_ERR_ARG, "sd_plan_pass_count: null argument");
+    if (dt != SD_C64 && dt != SD_C128) return fail(SD_ERR_ARG, "bad dtype");
+    *count = (int32_t)p->prog[dt].passes.size();
+    return SD_OK;
+}
+
+extern "C" sd_status sd_plan_export_pass(const sd_plan_t *p, sd_dtype dt, int32_t i,
+                                         sd_pass_view *v) {
+    if (!p || !v) return fail(SD_ERR_ARG, "sd_plan_export_pass: null argument");
+    if (dt != SD_C64 && dt != SD_C128) return fail(SD_ERR_ARG, "bad dtype");
+    const auto &P = p->prog[dt].passes;
+    if (i < 0 || i >= (int32_t)P.size()) return fail(SD_ERR_RANGE, "pass index out of range");
+    v->group = P[i].group;
+    v->n_terms = (int32_t)P[i].terms.size();
+    v->term_ids = P[i].terms.data();
+    v->rho = P[i].rho;
+    v->tile_log2 = P[i].D;
+    v->basis = P[i].basis.data();
+    v->coalesce_log2 = P[i].c;
+    v->free_mask = P[i].free_mask;
+    v->pivot_vec = P[i].u.data();
+    v->pivot_coord = P[i].mr.data();
+    v->cz_s = P[i].B.data();
+    v->zeta = P[i].zeta.data();
+    v->ztile = P[i].ztile.data();
+    v->coef = P[i].coef.data();
+    return SD_OK;
+}
+
+extern "C" void sd_plan_destroy(sd_plan_t *p) { delete p; }

@@ -1,0 +1,232 @@
+// Compilation of the commuting groups into device tile programs.
+//
+// The unitary of a commuting group, exp(-i tau sum_k c_k P_k), maps a basis
+// state |x> only into x ^ span{x_k} (every P_k flips the bits of its X part).
+// So it acts independently on every coset of the X span V of the group.  A
+// tile is one such coset, widened by the lowest address bits so that every
+// global access covers whole cache lines; it is staged on chip, transformed,
+// and written back: one HBM read and one write per group application.
+//
+// Inside a tile, with coordinates tau relative to a basis b_0..b_{D-1} of the
+// tile space (the first rho = dim V vectors span V), a term acts as
+//     P_k = i^{|x_k & z_k| - |alpha_k & omega_k|} (-1)^{z_k . x_T} X^alpha_k Z^omega_k
+// (alpha_k: coordinates of x_k; omega_k,i = z_k . b_i; x_T: the tile's base
+// address).  The paper's steps (i)-(iv) are run on this D-qubit tableau.
+// Because the X-span basis is made of terms' own X parts, the independent
+// set is those basis terms, step (i) finds full X rank (no H), step (ii) finds
+// an identity X block (no CNOT): the CNOT network of the physical-coordinate
+// circuit is exactly the change to tile coordinates, which costs nothing at
+// run time since it only changes which address lands in which on-chip slot.
+// Step (iii) gives the CZ/S layer and step (iv) H on all rho coordinates.
+//
+// A group whose tile would exceed the on-chip limit is split into commuting
+// sub-groups (any split is exact: the terms commute), each with its own tile.
+#include <algorithm>
+#include <cmath>
+
+#include "device_types.h"
+#include "sd_internal.h"
+
+namespace sd {
+
+namespace {
+
+// coordinates of v in basis b (v must lie in span b); result bit i <-> b[i]
+struct Coords {
+    Echelon e;
+    explicit Coords(const std::vector<uint64_t> &b) {
+        for (uint64_t v : b) e.insert(v);
+    }
+    bool solve(uint64_t v, uint32_t *out) const {
+        uint64_t used = 0;
+        uint64_t r = e.reduce(v, &used);
+        if (r) return false;
+        *out = (uint32_t)used;
+        return true;
+    }
+};
+
+sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
+                     const std::vector<int64_t> &ids, int D_target, int c_req,
+                     PassHost *ps) {
+    PassHost &p = *ps;
+    p.group = group;
+    p.terms = ids;
+    const int c = std::min(c_req, n);
+    // X-span basis from the terms' own X parts, in term order
+    Echelon vx;
+    std::vector<uint64_t> vbasis;
+    std::vector<int64_t> gen;  // generator term per basis vector
+    for (int64_t k : ids)
+        if (T[k].x && vx.insert(T[k].x)) {
+            vbasis.push_back(T[k].x);
+            gen.push_back(k);
+        }
+    p.rho = (int)vbasis.size();
+    // tile space: X span + low bits (coalescing) + more low bits up to D_target
+    Echelon w = vx;
+    std::vector<uint64_t> spect;
+    for (int q = 0; q < n; ++q) {
+        if (q >= c && w.dim() >= D_target) break;
+        uint64_t e = 1ull << q;
+        if (w.insert(e)) spect.push_back(e);
+    }
+    p.basis = vbasis;
+    p.basis.insert(p.basis.end(), spect.begin(), spect.end());
+    p.D = (int)p.basis.size();
+    if (p.D > 31) return fail(SD_ERR_INTERNAL, "tile dimension above 31");
+
+    // pivots: low bits 0..c-1 first (unit vectors), then the rest
+    Echelon piv;
+    for (int q = 0; q < c; ++q) piv.insert(1ull << q);
+    for (uint64_t b : p.basis) piv.insert(b);
+    if (piv.dim() != p.D) return fail(SD_ERR_INTERNAL, "tile basis rank mismatch");
+    std::vector<int> order(p.D);
+    for (int i = 0; i < p.D; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(),
+              [&](int a, int b) { return piv.piv[a] < piv.piv[b]; });
+    uint64_t pivmask = 0;
+    p.u.clear();
+    p.upiv.clear();
+    for (int i : order) {
+        p.u.push_back(piv.vec[i]);
+        p.upiv.push_back(piv.piv[i]);
+        pivmask |= 1ull << piv.piv[i];
+    }
+    p.c = c;
+    for (int q = 0; q < c; ++q)
+        if (p.upiv[q] != q || p.u[q] != (1ull << q))
+            return fail(SD_ERR_INTERNAL, "low pivots are not unit vectors");
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    p.free_mask = all & ~pivmask;
+
+    Coords co(p.basis);
+    p.mr.resize(p.D);
+    for (int i = 0; i < p.D; ++i)
+        if (!co.solve(p.u[i], &p.mr[i]))
+            return fail(SD_ERR_INTERNAL, "echelon vector outside the tile space");
+
+    // virtual tableau: generator rows first, then the group's terms in order
+    std::vector<Row> vrows;
+    std::vector<int64_t> vterm;
+    auto vrow = [&](int64_t k, Row *out, int *e) -> bool {
+        uint32_t alpha = 0;
+        if (!co.solve(T[k].x, &alpha)) return false;
+        uint32_t omega = 0;
+        for (int i = 0; i < p.D; ++i) omega |= (uint32_t)parity(T[k].z & p.basis[i]) << i;
+        *e = ((popc(T[k].x & T[k].z) - popc((uint64_t)(alpha & omega))) % 4 + 4) % 4;
+        *out = {alpha, omega, 0};
+        return true;
+    };
+    std::vector<int> ephase;
+    for (int64_t k : gen) {
+        Row r;
+        int e;
+        if (!vrow(k, &r, &e)) return fail(SD_ERR_INTERNAL, "generator outside tile space");
+        vrows.push_back(r);
+        vterm.push_back(k);
+        ephase.push_back(e);
+    }
+    for (int64_t k : ids) {
+        if (std::find(gen.begin(), gen.end(), k) != gen.end()) continue;
+        Row r;
+        int e;
+        if (!vrow(k, &r, &e)) return fail(SD_ERR_INTERNAL, "term outside tile space");
+        vrows.push_back(r);
+        vterm.push_back(k);
+        ephase.push_back(e);
+    }
+    for (int e : ephase)
+        if (e != 0 && e != 2) return fail(SD_ERR_INTERNAL, "non-Hermitian tile phase");
+
+    SynthOptions so;
+    so.skip_rule = true;
+    so.step_i = true;
+    SynthResult sr = synthesize(p.D, vrows, so);
+    if (!sr.ok) return fail(SD_ERR_INTERNAL, "tile synthesis: " + sr.error);
+    // expected shape: CZ/S on coordinates < rho, then H on every coordinate < rho
+    // (X-only coordinates may get their H first; it commutes with the CZ/S layer
+    // because such coordinates never appear in it).
+    p.B.assign(p.rho, 0u);
+    uint32_t hset = 0;
+    for (const Gate &g : sr.gates) {
+        if (g.kind == SD_GATE_CNOT) return fail(SD_ERR_INTERNAL, "tile synthesis emitted CNOT");
+        if (g.a >= p.rho || (g.b >= p.rho))
+            return fail(SD_ERR_INTERNAL, "tile gate outside the X span");
+        if (g.kind == SD_GATE_H) {
+            if ((hset >> g.a) & 1) return fail(SD_ERR_INTERNAL, "repeated tile H");
+            hset |= 1u << g.a;
+        } else {
+            if ((hset >> g.a) & 1 || (g.b >= 0 && ((hset >> g.b) & 1)))
+                return fail(SD_ERR_INTERNAL, "CZ/S after H in tile circuit");
+            if (g.kind == SD_GATE_S) {
+                p.B[g.a] ^= 1u << g.a;
+            } else {
+                p.B[g.a] ^= 1u << g.b;
+                p.B[g.b] ^= 1u << g.a;
+            }
+        }
+    }
+    const uint32_t rmask = (p.rho >= 32) ? ~0u : ((1u << p.rho) - 1);
+    if (hset != rmask) return fail(SD_ERR_INTERNAL, "tile H layer does not cover the X span");
+
+    // Lambda terms in the order of the group (vterm order is fine: they commute)
+    p.zeta.clear();
+    p.ztile.clear();
+    p.coef.clear();
+    p.terms = vterm;
+    for (size_t i = 0; i < vterm.size(); ++i) {
+        const int64_t k = vterm[i];
+        p.zeta.push_back((uint32_t)sr.zmask[i]);
+        p.ztile.push_back(T[k].z);
+        double s = (sr.sign[i] ? -1.0 : 1.0) * (ephase[i] == 2 ? -1.0 : 1.0);
+        p.coef.push_back(T[k].c * s);
+    }
+    return SD_OK;
+}
+
+}  // namespace
+
+sd_status compile_program(int n, const std::vector<Term> &T,
+                          const std::vector<std::vector<int64_t>> &groups,
+                          int D_max, int c, Program *out) {
+    Program &P = *out;
+    P.D_max = D_max;
+    P.c = c;
+    P.passes.clear();
+    P.group_first.assign(1, 0);
+    const int cc = std::min(c, n);
+    const int Dcap = std::min(D_max, n);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        // split into sub-groups whose tile space (X span + low bits) fits
+        std::vector<Echelon> spaces;
+        std::vector<std::vector<int64_t>> subs;
+        for (int64_t k : groups[g]) {
+            const uint64_t x = T[k].x;
+            int pick = -1;
+            for (size_t s = 0; s < subs.size() && pick < 0; ++s)
+                if ((int)subs[s].size() < kMaxPassTerms && spaces[s].contains(x)) pick = (int)s;
+            for (size_t s = 0; s < subs.size() && pick < 0; ++s)
+                if ((int)subs[s].size() < kMaxPassTerms && spaces[s].dim() < Dcap) pick = (int)s;
+            if (pick < 0) {
+                Echelon e;
+                for (int q = 0; q < cc; ++q) e.insert(1ull << q);
+                spaces.push_back(e);
+                subs.emplace_back();
+                pick = (int)subs.size() - 1;
+            }
+            spaces[pick].insert(x);
+            subs[pick].push_back(k);
+        }
+        for (auto &s : subs) {
+            PassHost ps;
+            sd_status st = build_pass(n, T, (int32_t)g, s, Dcap, cc, &ps);
+            if (st != SD_OK) return st;
+            P.passes.push_back(std::move(ps));
+        }
+        P.group_first.push_back((int32_t)P.passes.size());
+    }
+    return SD_OK;
+}
+
+}  // namespace sd

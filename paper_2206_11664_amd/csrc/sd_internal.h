@@ -1,0 +1,157 @@
+// Internal types of the sd library (host side).  Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sd.h"
+
+namespace sd {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+sd_status fail(sd_status s, const std::string &msg);  // sets sd_last_error
+
+// ---------------------------------------------------------------------------
+// GF(2) helpers on 64-bit rows
+// ---------------------------------------------------------------------------
+inline int popc(uint64_t v) { return __builtin_popcountll(v); }
+inline int parity(uint64_t v) { return __builtin_popcountll(v) & 1; }
+inline int ctz(uint64_t v) { return __builtin_ctzll(v); }
+
+// Incremental echelon basis: every stored vector has a 1 at its pivot and 0
+// at every other stored pivot.  comb[i] records which inserted generators
+// (by insertion index, up to 64) XOR to vec[i].
+struct Echelon {
+    std::vector<uint64_t> vec, comb;
+    std::vector<int> piv;
+    int inserted = 0;
+    // Reduce v against the basis; returns the remainder, and the combination
+    // of basis vectors used in *used (as generator combination).
+    uint64_t reduce(uint64_t v, uint64_t *used = nullptr) const;
+    // Insert; returns true if v was independent.
+    bool insert(uint64_t v);
+    bool contains(uint64_t v) const { return reduce(v) == 0; }
+    int dim() const { return (int)vec.size(); }
+};
+
+int gf2_rank(std::vector<uint64_t> rows);
+
+// ---------------------------------------------------------------------------
+// Hamiltonian
+// ---------------------------------------------------------------------------
+struct Term {
+    uint64_t x, z;  // symplectic masks; Hermitian Pauli = i^{|x&z|} X^x Z^z
+    double c;
+    int64_t src;    // input index of first occurrence
+};
+
+}  // namespace sd
+
+struct sd_hamiltonian {
+    int32_t n = 0;
+    std::vector<sd::Term> terms;
+    // flat views for sd_hamiltonian_terms
+    std::vector<uint64_t> xs, zs;
+    std::vector<double> cs;
+    std::vector<int64_t> srcs;
+};
+
+namespace sd {
+
+// ---------------------------------------------------------------------------
+// Clifford synthesis on the binary tableau (paper steps (i)-(iv))
+// ---------------------------------------------------------------------------
+struct Gate {
+    int32_t kind, a, b;  // SD_GATE_*, qubits (b = -1 for one-qubit gates)
+};
+
+// A row of the tableau [X | Z | r] (Eq. binary_tableau), qubit q = bit q.
+struct Row {
+    uint64_t x, z;
+    int r;
+};
+
+// Conjugation rules U P U^dagger of the tableau (Sec. "Tableau Representation",
+// gate table).  CNOT uses z_c ^= z_t (see DESIGN notes: the printed z-rule of
+// the CNOT row disagrees with the two-qubit table; the standard rule agrees).
+void apply_gate(Row &row, const Gate &g);
+
+struct SynthOptions {
+    bool skip_rule = true;     // {I,Z}/{I,X} qubit pre-pass
+    bool step_i = true;        // run step (i), maximise X-block rank with H
+};
+
+struct SynthResult {
+    bool ok = false;
+    std::string error;
+    std::vector<Gate> gates;            // application order
+    std::vector<int64_t> independent;   // indices into the input list
+    std::vector<uint64_t> zmask;        // per input term
+    std::vector<int8_t> sign;           // per input term
+    int n_h_first = 0, n_h_last = 0, n_cnot_controls = 0, n_diag = 0;
+};
+
+// Appendix algorithm: linearly independent rows over the columns
+// x_{act[0..]} then z_{act[0..]}; returns indices into `rows`, final order.
+std::vector<int64_t> independent_rows(const std::vector<Row> &rows,
+                                      const std::vector<int> &act);
+
+// Steps (i)-(iv) for one commuting set of n-qubit Paulis.
+SynthResult synthesize(int n, const std::vector<Row> &terms, const SynthOptions &opt);
+
+// ---------------------------------------------------------------------------
+// Device tile programs
+// ---------------------------------------------------------------------------
+constexpr int kMaxTileLog2 = 13;   // on-chip tile limit (LDS, FP64 staging)
+constexpr int kMinTileLog2 = 6;
+
+struct PassHost {
+    int32_t group = -1;
+    std::vector<int64_t> terms;     // merged-term ids
+    int rho = 0, D = 0, c = 0;      // active dims, tile dims, coalescing pivots
+    std::vector<uint64_t> basis;    // b_0..b_{D-1}: X-span basis, then spectators
+    uint64_t free_mask = 0;         // non-pivot bit positions
+    std::vector<uint64_t> u;        // echelon vectors sorted by pivot (D)
+    std::vector<int> upiv;          // their pivots (ascending, first c = 0..c-1)
+    std::vector<uint32_t> mr;       // column i = tile coords of u[i] (D-bit)
+    std::vector<uint32_t> B;        // rho rows of the CZ/S form (bit j of B[i])
+    std::vector<uint32_t> zeta;     // per term, D-bit mask of Lambda
+    std::vector<uint64_t> ztile;    // per term, physical z for the tile sign
+    std::vector<double> coef;       // per term, c_k (-1)^{r_k} i^{e_k}
+};
+
+struct Program {
+    int D_max = 13, c = 4;
+    std::vector<PassHost> passes;        // group order, sub-groups in order
+    std::vector<int32_t> group_first;    // first pass of group g (K+1 entries)
+};
+
+sd_status compile_program(int n, const std::vector<Term> &terms,
+                          const std::vector<std::vector<int64_t>> &groups,
+                          int D_max, int c, Program *out);
+
+// bytes of the packed device records of a program (device.hip)
+int64_t pack_size(const Program &P);
+
+}  // namespace sd
+
+struct sd_plan_s {
+    int32_t n = 0;
+    std::vector<sd::Term> terms;
+    std::vector<std::vector<int64_t>> groups;
+    std::vector<sd::SynthResult> circuits;      // paper circuit per group
+    std::vector<std::vector<int32_t>> gate_flat; // for export
+    sd::Program prog[2];                        // [SD_C64], [SD_C128]
+    int64_t paper_model_passes = 0;
+    double plan_seconds = 0;
+    // device side
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t ws_needed = 0;
+    int64_t ws_off_prog[2] = {0, 0};   // byte offsets of packed pass tables
+    int64_t ws_off_scratch = 0;        // reduction scratch
+    bool bound = false;
+};

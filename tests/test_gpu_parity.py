@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars (from the workload definitions): complex128 L2 error <= 1e-10; complex64
+L2 error <= 1e-5 and fidelity >= 1 - 1e-6 (the complex64 bar is stated for
+1000 steps; shorter runs must meet it too).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+from paper_2206_11664_amd import sd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {sd.SD_C128: 1e-10, sd.SD_C64: 1e-5}
+TDT = {sd.SD_C128: torch.complex128, sd.SD_C64: torch.complex64}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(oracle_lib):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sd.lib()
+
+
+def gpu_evolve(m, psi0, dtype, dt, steps, order, opts=None, plan=None):
+    print(f"[gpu] {m.name} n={m.n} dtype={dtype} steps={steps} order={order}", flush=True)
+    if plan is None:
+        o = sd.sd_plan_options_default()
+        for k, v in (opts or {}).items():
+            setattr(o, k, v)
+        plan = sd.Plan(m.n, m.paulis, m.coeffs, o).bind()
+    psi = torch.from_numpy(np.asarray(psi0, dtype=np.complex128)).to(TDT[dtype]).cuda()
+    plan.evolve(psi, dt, steps, order)
+    torch.cuda.synchronize()
+    return psi.cpu().numpy().astype(np.complex128), plan
+
+
+def l2(a, b):
+    return float(np.linalg.norm(a - b))
+
+
+def check(m, dtype, dt, steps, order, opts=None, psi0=None):
+    psi0 = m.initial_state() if psi0 is None else psi0
+    got, plan = gpu_evolve(m, psi0, dtype, dt, steps, order, opts)
+    want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, dt, steps, order)
+    err = l2(got, want)
+    assert err <= TOL[dtype], (m.name, dtype, err)
+    if dtype == sd.SD_C64:
+        assert oracle.fidelity(got, want) >= 1 - 1e-6
+    return plan, got, want
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_config1_tfim_chain_full(dtype):
+    m = workloads.tfim_chain(12)
+    check(m, dtype, m.dt, m.steps, m.order)
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_xxz_periodic_order2(dtype):
+    m = workloads.xxz_chain(n=14, steps=40)
+    check(m, dtype, m.dt, m.steps, 2)
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_random_klocal_reduced(dtype):
+    m = workloads.random_klocal(n=16, m=400, seed=3, init_seed=30)
+    check(m, dtype, 0.01, 10, 1)
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_jw_fermionic_reduced(dtype):
+    m = workloads.jw_fermionic(n=12, total=700)
+    check(m, dtype, 0.02, 5, 2, psi0=workloads.random_state(12, 5))
+
+
+@pytest.mark.parametrize("tile", [6, 8, 10, 13])
+def test_tile_sizes_and_split_groups(tile):
+    # small tiles force many tiles per pass and sub-group splits
+    m = workloads.random_klocal(n=15, m=200, seed=8, init_seed=2)
+    opts = dict(tile_log2_c64=tile, tile_log2_c128=tile)
+    check(m, sd.SD_C128, 0.03, 3, 1, opts)
+    check(m, sd.SD_C64, 0.03, 3, 1, opts)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_tiny_systems(n):
+    rng = np.random.default_rng(n)
+    ps = ["".join("IXYZ"[int(rng.integers(4))] for _ in range(n)) for _ in range(6)]
+    m = workloads.Model("tiny", n, ps, rng.normal(size=6))
+    psi0 = workloads.random_state(n, 1)
+    for dt in (sd.SD_C128, sd.SD_C64):
+        check(m, dt, 0.2, 4, 2, psi0=psi0)
+
+
+def test_diagonal_only_and_identity_terms():
+    n = 11
+    ps = ["I" * n] + ["".join("IZ"[(q * 7 + k) % 3 == 0] for q in range(n)) for k in range(30)]
+    m = workloads.Model("allz", n, ps, np.linspace(-1, 1, len(ps)))
+    check(m, sd.SD_C128, 0.3, 3, 1, psi0=workloads.random_state(n, 2))
+
+
+def test_empty_hamiltonian_is_identity():
+    n = 6
+    plan = sd.Plan(n, [], []).bind()
+    psi0 = workloads.random_state(n, 4)
+    psi = torch.from_numpy(psi0).cuda()
+    plan.evolve(psi, 0.1, 5, 1)
+    torch.cuda.synchronize()
+    assert np.array_equal(psi.cpu().numpy(), psi0)
+
+
+def test_expectation_matches_oracle():
+    m = workloads.random_klocal(n=14, m=300, seed=4, init_seed=9)
+    psi0 = m.initial_state()
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    want = oracle.energy(m.n, m.paulis, m.coeffs, psi0)
+    for dtype, tol in ((sd.SD_C128, 1e-10), (sd.SD_C64, 1e-5)):
+        psi = torch.from_numpy(psi0).to(TDT[dtype]).cuda()
+        e = plan.expectation(psi)
+        assert abs(e - want) <= tol * max(1.0, abs(want)), (dtype, e, want)
+
+
+def test_norm_and_inner():
+    n = 17
+    a = workloads.random_state(n, 1)
+    b = workloads.random_state(n, 2)
+    for dtype in (sd.SD_C128, sd.SD_C64):
+        ta = torch.from_numpy(a).to(TDT[dtype]).cuda()
+        tb = torch.from_numpy(b).to(TDT[dtype]).cuda()
+        ref_a = ta.cpu().numpy().astype(np.complex128)
+        ref_b = tb.cpu().numpy().astype(np.complex128)
+        assert abs(sd.sd_norm2(ta, n) - np.vdot(ref_a, ref_a).real) < 1e-12
+        ov = sd.sd_inner(ta, tb, n)
+        assert abs(ov - np.vdot(ref_a, ref_b)) < 1e-12
+
+
+def test_split_runs_are_bit_identical():
+    m = workloads.random_klocal(n=15, m=250, seed=6, init_seed=7)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    psi0 = torch.from_numpy(m.initial_state()).to(torch.complex64).cuda()
+    a = psi0.clone()
+    plan.evolve(a, 0.02, 10, 1)
+    b = psi0.clone()
+    plan.evolve(b, 0.02, 5, 1)
+    plan.evolve(b, 0.02, 5, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_c64_long_run_fidelity():
+    # 1000 second-order steps, the complex64 bar's own length
+    m = workloads.xxz_chain(n=12, steps=1000)
+    check(m, sd.SD_C64, 0.05, 1000, 2)
+
+
+def _random_state_torch(n, seed):
+    g = torch.Generator().manual_seed(seed)
+    re = torch.randn(1 << n, dtype=torch.float64, generator=g)
+    im = torch.randn(1 << n, dtype=torch.float64, generator=g)
+    psi = torch.complex(re, im)
+    del re, im
+    psi /= torch.linalg.vector_norm(psi)
+    return psi
+
+
+def test_full_size_n28_properties():
+    # the benchmark workload at full size: time reversibility of the symmetric
+    # second-order product, norm conservation, c64 against c128
+    m = workloads.random_klocal(n=28)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    print("[gpu] n28 reversibility", flush=True)
+    d128 = _random_state_torch(28, 11).cuda()
+    a = d128.clone()
+    plan.evolve(a, 0.01, 2, 2)
+    plan.evolve(a, -0.01, 2, 2)
+    torch.cuda.synchronize()
+    assert float(torch.linalg.vector_norm(a - d128)) < 1e-10
+    del a
+    b = d128.clone()
+    plan.evolve(b, 0.01, 2, 1)
+    c = d128.to(torch.complex64)
+    plan.evolve(c, 0.01, 2, 1)
+    torch.cuda.synchronize()
+    assert abs(sd.sd_norm2(b, 28) - 1) < 1e-12
+    assert abs(sd.sd_norm2(c, 28) - 1) < 1e-5
+    assert float(torch.linalg.vector_norm(c.to(torch.complex128) - b)) < 1e-5
+
+
+def test_full_size_n28_widest_group_vs_oracle():
+    # one application of the benchmark's widest commuting group (largest X
+    # span, several tile passes) at n = 28, same tile configuration as the
+    # benchmark, against the oracle on the full 2^28 vector
+    m = workloads.random_klocal(n=28)
+    full = sd.Plan(m.n, m.paulis, m.coeffs)
+    passes = full.passes(sd.SD_C64)
+    g = max(range(full.info.n_groups),
+            key=lambda gi: sum(p["rho"] for p in passes if p["group"] == gi))
+    ids = full.group(g).term_ids
+    t = oracle.build_terms(m.n, m.paulis, m.coeffs)
+    letters = {(0, 0): "I", (1, 0): "X", (0, 1): "Z", (1, 1): "Y"}
+    ps = ["".join(letters[((int(t.x[k]) >> q) & 1, (int(t.z[k]) >> q) & 1)] for q in range(28))
+          for k in ids]
+    cs = [float(t.c[k]) for k in ids]
+    sub = workloads.Model("group", 28, ps, np.array(cs))
+    plan = sd.Plan(28, ps, cs).bind()
+    assert plan.info.n_groups == 1
+    print(f"[gpu] n28 group {g}: {len(ids)} terms, passes "
+          f"{[p['rho'] for p in plan.passes(sd.SD_C64)]}", flush=True)
+    psi0 = _random_state_torch(28, 5)
+    want = oracle.evolve(28, sub.paulis, sub.coeffs, psi0.numpy(), 0.37, 1, 1)
+    for dtype in (sd.SD_C128, sd.SD_C64):
+        d = psi0.to(TDT[dtype]).cuda()
+        plan.evolve(d, 0.37, 1, 1)
+        got = d.cpu().numpy().astype(np.complex128)
+        del d
+        err = l2(got, want)
+        print(f"[gpu] n28 group dtype={dtype} L2={err:.3e}", flush=True)
+        assert err <= (1e-10 if dtype == sd.SD_C128 else 1e-6)

@@ -1,0 +1,314 @@
+"""Host-side planner tests through the C ABI (no GPU calls): parsing, grouping
+bit-exact against the oracle, the paper's worked examples, brute-force
+checks that every synthesised Clifford diagonalises its group, and an
+emulation of the compiled tile programs against the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2206_11664_amd import sd
+from tests import dense, tile_emulator
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _libs(oracle_lib):
+    sd.lib()
+
+
+def plan_for(n, paulis, coeffs, **opt):
+    o = sd.sd_plan_options_default()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    h = sd.sd_hamiltonian_create(n, paulis, coeffs)
+    p = sd.sd_plan(h, o)
+    return h, p
+
+
+def groups_of(p):
+    info = sd.sd_plan_info_get(p)
+    return [list(sd.sd_plan_export_group(p, g).term_ids) for g in range(info.n_groups)]
+
+
+def pauli_str(n, x, z):
+    return "".join({(0, 0): "I", (1, 0): "X", (0, 1): "Z", (1, 1): "Y"}[((x >> q) & 1, (z >> q) & 1)]
+                   for q in range(n))
+
+
+# --- parsing ---------------------------------------------------------------------
+def test_masks_bit_exact_vs_oracle():
+    for m in (workloads.tfim_chain(12), workloads.xxz_chain(26),
+              workloads.random_klocal(n=28), workloads.jw_fermionic(n=12, total=400)):
+        h = sd.sd_hamiltonian_create(m.n, m.paulis, m.coeffs)
+        n, x, z, c, src = sd.sd_hamiltonian_terms(h)
+        t = oracle.build_terms(m.n, m.paulis, m.coeffs)
+        assert n == m.n
+        assert np.array_equal(x, t.x) and np.array_equal(z, t.z)
+        assert np.array_equal(src, t.source)
+        assert np.allclose(c, t.c, rtol=0, atol=1e-15)
+        sd.sd_hamiltonian_destroy(h)
+
+
+def test_sparse_and_dense_forms_agree():
+    h1 = sd.sd_hamiltonian_create(5, ["X0 Y3 Z4", "Z1"], [1.0, 2.0])
+    h2 = sd.sd_hamiltonian_create(5, ["XIIYZ", "IZIII"], [1.0, 2.0])
+    a, b = sd.sd_hamiltonian_terms(h1), sd.sd_hamiltonian_terms(h2)
+    assert all(np.array_equal(u, v) for u, v in zip(a[1:], b[1:]))
+
+
+@pytest.mark.parametrize("bad,status", [(["XQ"], sd.SD_ERR_PARSE), (["X0 X0"], sd.SD_ERR_PARSE),
+                                        (["X7"], sd.SD_ERR_RANGE), (["XXX"], sd.SD_ERR_PARSE)])
+def test_parse_errors(bad, status):
+    with pytest.raises(sd.SdError) as e:
+        sd.sd_hamiltonian_create(2, bad, [1.0])
+    assert e.value.status == status
+
+
+def test_argument_errors():
+    with pytest.raises(sd.SdError) as e:
+        sd.sd_hamiltonian_create(64, ["X0"], [1.0])
+    assert e.value.status == sd.SD_ERR_RANGE
+    with pytest.raises(sd.SdError) as e:
+        sd.sd_hamiltonian_create(2, ["X0"], [float("nan")])
+    assert e.value.status == sd.SD_ERR_ARG
+    with pytest.raises(sd.SdError) as e:
+        sd.sd_hamiltonian_create_masks(2, [4], [0], [1.0])
+    assert e.value.status == sd.SD_ERR_RANGE
+    o = sd.sd_plan_options_default()
+    o.tile_log2_c64 = 20
+    h = sd.sd_hamiltonian_create(2, ["XX"], [1.0])
+    with pytest.raises(sd.SdError) as e:
+        sd.sd_plan(h, o)
+    assert e.value.status == sd.SD_ERR_RANGE
+
+
+# --- grouping ------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["tfim", "xxz", "klocal", "jw", "tfim_fc"])
+def test_grouping_bit_exact_vs_oracle(which):
+    m = {"tfim": lambda: workloads.tfim_chain(12),
+         "xxz": lambda: workloads.xxz_chain(26),
+         "klocal": lambda: workloads.random_klocal(n=28),
+         "jw": lambda: workloads.jw_fermionic(n=16, total=1500),
+         "tfim_fc": lambda: workloads.tfim_fully_connected(20)}[which]()
+    h, p = plan_for(m.n, m.paulis, m.coeffs)
+    got = groups_of(p)
+    want = oracle.first_fit_groups(oracle.build_terms(m.n, m.paulis, m.coeffs))
+    assert got == want
+    sd.sd_plan_destroy(p)
+    sd.sd_hamiltonian_destroy(h)
+
+
+# --- the paper's worked examples -----------------------------------------------------
+def test_e5_independent_set():
+    g = json.load(open(os.path.join(GOLD, "e5_independent_set.json")))
+    h, p = plan_for(g["n"], g["terms"], [1.0] * len(g["terms"]))
+    assert len(groups_of(p)) == 1
+    ex = sd.sd_plan_export_group(p, 0)
+    assert [int(i) + 1 for i in ex.independent] == g["independent_rows_1based"]
+
+
+def _zstr_to_mask(s):
+    sign = -1 if s[0] == "-" else 1
+    body = s[1:]
+    mask = 0
+    for tok in body.split("Z")[1:]:
+        mask |= 1 << (int(tok) - 1)
+    return sign, mask
+
+
+def test_e4_circuit_and_diagonal_form():
+    g = json.load(open(os.path.join(GOLD, "e4_diagonalization.json")))
+    h, p = plan_for(g["n"], g["terms"], [1.0] * len(g["terms"]))
+    assert len(groups_of(p)) == 1
+    ex = sd.sd_plan_export_group(p, 0)
+    assert list(ex.independent) == g["independent_terms"]
+    gates = ex.gates
+    c = g["circuit_paper_1based"]
+    # layers in application order: H (step i), CNOT, CZ/S, H (step iv)
+    kinds = [k for k, _, _ in gates]
+    nh1 = len(c["H_first"])
+    assert sorted(a + 1 for k, a, _ in gates[:nh1] if k == "H") == c["H_first"]
+    rest = gates[nh1:]
+    cn = [(a + 1, b + 1) for k, a, b in rest if k == "CNOT"]
+    assert cn == [tuple(v) for v in c["CNOT"]]
+    cz = sorted((a + 1, b + 1) for k, a, b in rest if k == "CZ")
+    assert cz == sorted(tuple(v) for v in c["CZ"])
+    s = sorted(a + 1 for k, a, _ in rest if k == "S")
+    assert s == c["S"]
+    tail = [a + 1 for k, a, _ in gates[-4:]]
+    assert all(k == "H" for k in kinds[-4:]) and sorted(tail) == c["H_last"]
+    assert len(gates) == nh1 + len(c["CNOT"]) + len(c["CZ"]) + len(c["S"]) + 4
+    for k, want in enumerate(g["diagonal_paper"]):
+        sign, mask = _zstr_to_mask(want)
+        assert int(ex.zmask[k]) == mask, (k, want)
+        assert (-1) ** int(ex.sign[k]) == sign, (k, want)
+
+
+# --- brute force: every synthesised circuit diagonalises its group --------------------
+def random_commuting_hamiltonian(rng, n, m):
+    out = []
+    while len(out) < m:
+        s = "".join("IXYZ"[int(rng.integers(4))] for _ in range(n))
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_paper_circuits_diagonalise_dense(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(3, 7))
+    ps = random_commuting_hamiltonian(rng, n, 30)
+    cs = rng.normal(size=len(ps))
+    h, p = plan_for(n, ps, cs)
+    t = oracle.build_terms(n, ps, cs)
+    for gi, g in enumerate(groups_of(p)):
+        ex = sd.sd_plan_export_group(p, gi)
+        C = dense.circuit_matrix(n, ex.gates)
+        for j, k in enumerate(g):
+            P = dense.pauli_matrix(pauli_str(n, int(t.x[k]), int(t.z[k])))
+            want = (-1) ** int(ex.sign[j]) * dense.zstring(n, int(ex.zmask[j]))
+            assert np.allclose(C @ P @ C.conj().T, want, atol=1e-12), (gi, j)
+
+
+def test_paper_circuits_diagonalise_large_groups():
+    # n = 28 random k-local groups: propagate each Pauli through the gate list
+    # with the single- and two-qubit conjugation tables, qubit by qubit.
+    m = workloads.random_klocal(n=28)
+    h, p = plan_for(m.n, m.paulis, m.coeffs)
+    n, x, z, c, _ = sd.sd_hamiltonian_terms(h)
+    for gi, g in enumerate(groups_of(p)):
+        ex = sd.sd_plan_export_group(p, gi)
+        for j, k in enumerate(g):
+            ph, xx, zz = _propagate(int(x[k]), int(z[k]), ex.gates)
+            assert xx == 0 and zz == int(ex.zmask[j])
+            assert ph == (2 if ex.sign[j] else 0)
+
+
+def _propagate(x, z, gates):
+    """U P U^dagger gate by gate, with P = i^{phase} prod_q sigma(x_q, z_q)
+    (sigma(1,1) = Y).  Single-qubit images: H: X->Z, Z->X, Y->-Y;  S: X->Y,
+    Y->-X, Z->Z.  CNOT(c,t): X_c->X_c X_t, Z_t->Z_c Z_t, X_t, Z_c fixed.
+    CZ(a,b): X_a->X_a Z_b, X_b->Z_a X_b.  Products are multiplied out with the
+    single-qubit Pauli multiplication table."""
+    # represent as dict qubit -> letter, plus phase (power of i)
+    n = 64
+    P = {q: _letter((x >> q) & 1, (z >> q) & 1) for q in range(n) if ((x | z) >> q) & 1}
+    phase = 0
+    for kind, a, b in gates:
+        if kind in ("H", "S"):
+            l = P.get(a, "I")
+            img = {"H": {"X": (0, "Z"), "Z": (0, "X"), "Y": (2, "Y")},
+                   "S": {"X": (0, "Y"), "Y": (2, "X"), "Z": (0, "Z")}}[kind].get(l)
+            if img:
+                phase += img[0]
+                P[a] = img[1]
+        else:
+            la, lb = P.get(a, "I"), P.get(b, "I")
+            # images of the generators on (a, b)
+            if kind == "CNOT":
+                gen = {"Xa": ("X", "X"), "Za": ("Z", "I"), "Xb": ("I", "X"), "Zb": ("Z", "Z")}
+            else:
+                gen = {"Xa": ("X", "Z"), "Za": ("Z", "I"), "Xb": ("Z", "X"), "Zb": ("I", "Z")}
+            # decompose la (x) lb = i^{#Y} X^xa Z^za X^xb Z^zb (order X_a Z_a X_b Z_b)
+            xa, za = _bits(la)
+            xb, zb = _bits(lb)
+            ph = (xa & za) + (xb & zb)
+            cur = ("I", "I")
+            for use, gname in ((xa, "Xa"), (za, "Za"), (xb, "Xb"), (zb, "Zb")):
+                if use:
+                    g = gen[gname]
+                    p1, r1 = _mul(cur[0], g[0])
+                    p2, r2 = _mul(cur[1], g[1])
+                    ph += p1 + p2
+                    cur = (r1, r2)
+            phase += ph
+            P[a], P[b] = cur
+    xx = zz = 0
+    for q, l in P.items():
+        bx, bz = _bits(l)
+        xx |= bx << q
+        zz |= bz << q
+    # P = i^{phase} prod sigma; a Z-string has no Y, so nothing to convert
+    return phase % 4, xx, zz
+
+
+def _letter(bx, bz):
+    return {(0, 0): "I", (1, 0): "X", (0, 1): "Z", (1, 1): "Y"}[(bx, bz)]
+
+
+def _bits(l):
+    return {"I": (0, 0), "X": (1, 0), "Z": (0, 1), "Y": (1, 1)}[l]
+
+
+def _mul(a, b):
+    """a*b = i^k c for single-qubit Paulis."""
+    if a == "I":
+        return 0, b
+    if b == "I":
+        return 0, a
+    if a == b:
+        return 0, "I"
+    cyc = {("X", "Y"): "Z", ("Y", "Z"): "X", ("Z", "X"): "Y"}
+    if (a, b) in cyc:
+        return 1, cyc[(a, b)]
+    return 3, cyc[(b, a)]
+
+
+def test_tableau_tables_by_dense_conjugation():
+    # the paper's single- and two-qubit conjugation tables, checked with matrices
+    H, S = dense.H, dense.S
+    X, Y, Z = dense.X, dense.Y, dense.Z
+    assert np.allclose(H @ X @ H.conj().T, Z) and np.allclose(H @ Y @ H.conj().T, -Y)
+    assert np.allclose(S @ X @ S.conj().T, Y) and np.allclose(S @ Y @ S.conj().T, -X)
+    CN = dense.cnot(2, 0, 1)
+    k = dense.kron_ops
+    assert np.allclose(CN @ k(2, {1: Z}) @ CN.T, k(2, {0: Z, 1: Z}))   # I1 Z2 -> Z1 Z2
+    assert np.allclose(CN @ k(2, {0: Y, 1: Y}) @ CN.T, -k(2, {0: X, 1: Z}))
+    # and the propagation helper used above agrees on every 2-qubit Pauli
+    for l1 in "IXYZ":
+        for l2 in "IXYZ":
+            for gate in (("CNOT", 0, 1), ("CZ", 0, 1), ("H", 0, -1), ("S", 1, -1)):
+                x = (l1 in "XY") | ((l2 in "XY") << 1)
+                z = (l1 in "ZY") | ((l2 in "ZY") << 1)
+                ph, xx, zz = _propagate(x, z, [gate])
+                U = dense.gate_matrix(2, gate)
+                P = dense.pauli_matrix(l1 + l2)
+                want = (1j) ** ph * dense.pauli_matrix(pauli_str(2, xx, zz))
+                assert np.allclose(U @ P @ U.conj().T, want)
+
+
+# --- tile programs vs the oracle (emulated on the CPU) ---------------------------------
+@pytest.mark.parametrize("case", ["klocal", "xxz", "tfim", "jw", "rand"])
+@pytest.mark.parametrize("dtype", [sd.SD_C64, sd.SD_C128])
+def test_tile_program_emulation_matches_oracle(case, dtype):
+    rng = np.random.default_rng(7)
+    if case == "klocal":
+        m = workloads.random_klocal(n=9, m=60, seed=5, init_seed=6)
+        opts = dict(tile_log2_c64=6, tile_log2_c128=6, coalesce_log2_c64=2, coalesce_log2_c128=1)
+    elif case == "xxz":
+        m = workloads.xxz_chain(n=8, steps=3)
+        opts = dict(tile_log2_c64=6, tile_log2_c128=7)
+    elif case == "tfim":
+        m = workloads.tfim_chain(7)
+        opts = {}
+    elif case == "jw":
+        m = workloads.jw_fermionic(n=8, total=120)
+        opts = dict(tile_log2_c64=7, tile_log2_c128=6)
+    else:
+        m = workloads.random_klocal(n=8, m=40, seed=9, init_seed=1)
+        m.paulis = random_commuting_hamiltonian(rng, 8, 40)
+        opts = dict(tile_log2_c64=6, tile_log2_c128=6)
+    h, p = plan_for(m.n, m.paulis, m.coeffs, **opts)
+    info = sd.sd_plan_info_get(p)
+    passes = [sd.sd_plan_export_pass(p, dtype, i) for i in range(sd.sd_plan_pass_count(p, dtype))]
+    psi0 = workloads.random_state(m.n, 3)
+    order = 2 if case == "xxz" else 1
+    got = tile_emulator.evolve(psi0, m.n, passes, [q["group"] for q in passes], info.n_groups,
+                               0.11, 3, order)
+    want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.11, 3, order)
+    assert np.abs(got - want).max() < 1e-12
