@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -55,6 +56,14 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         int f = 0;
         for (int q = 0; q < n; ++q)
             if ((p.free_mask >> q) & 1) d.free_pos[f++] = (uint8_t)q;
+        d.nr = p.nr;
+        d.lam_round = p.lam_round;
+        for (int r = 0; r < 4; ++r) {
+            for (int b = 0; b < 5; ++b) d.reg[r][b] = p.reg[r][b];
+            d.bmask[r] = p.bmask[r];
+        }
+        for (int w = 0; w < 33; ++w) d.bucket[w] = p.bucket.empty() ? 0 : p.bucket[w];
+        d.coef_abs_sum = p.coef_abs_sum;
         std::memcpy(buf.data() + i * sizeof(PassDev), &d, sizeof(d));
         uint8_t *t = buf.data() + toff;
         const int m = d.m;
@@ -216,6 +225,314 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_tile: register-round tile pass (tiles of 2^D amplitudes, D >= kTileMinD)
+// ---------------------------------------------------------------------------
+// A block of 2^(D-5) threads owns one tile at a time; every thread holds 32
+// amplitudes in FP64 registers.  In the round of chunk r the 32 amplitudes of
+// a thread differ in the 5 tile coordinates reg[r] and share the others
+// (taken from the thread index), so the butterflies of those coordinates run
+// in registers; between rounds the tile is exchanged through LDS.  The LDS
+// slot of tile coordinate t is t ^ fold(t >> 3), fold = XOR of its 3-bit
+// groups: whenever the three lowest thread-index bits address three adjacent
+// coordinates, the 8 lanes of a 128-byte LDS phase land in distinct banks.
+constexpr int kE = 32;
+constexpr int kTileMinD = 10;
+
+__device__ __forceinline__ uint32_t lds_slot(uint32_t t) {
+    uint32_t h = t >> 3;
+    h ^= (h >> 3) ^ (h >> 6) ^ (h >> 9);
+    return t ^ (h & 7u);
+}
+
+// e^{i theta} in FP64: Taylor polynomials of cos and sin at theta / 2^halv
+// (|theta / 2^halv| <= 1/4, truncation < 1e-17), then halv double-angle steps.
+__device__ __forceinline__ void cis(double th, int halv, double &c, double &s) {
+    const double x = ldexp(th, -halv);
+    const double x2 = x * x;
+    double pc = 1.0 / 479001600.0;
+    pc = fma(pc, x2, -1.0 / 3628800.0);
+    pc = fma(pc, x2, 1.0 / 40320.0);
+    pc = fma(pc, x2, -1.0 / 720.0);
+    pc = fma(pc, x2, 1.0 / 24.0);
+    pc = fma(pc, x2, -0.5);
+    c = fma(pc, x2, 1.0);
+    double ps = 1.0 / 6227020800.0;
+    ps = fma(ps, x2, -1.0 / 39916800.0);
+    ps = fma(ps, x2, 1.0 / 362880.0);
+    ps = fma(ps, x2, -1.0 / 5040.0);
+    ps = fma(ps, x2, 1.0 / 120.0);
+    ps = fma(ps, x2, -1.0 / 6.0);
+    s = fma(x * x2, ps, x);
+    for (int i = 0; i < halv; ++i) {
+        const double c2 = fma(c, c, -s * s);
+        s = 2.0 * c * s;
+        c = c2;
+    }
+}
+
+// a * i^e, e in 0..3
+__device__ __forceinline__ double2 rot_ipow(double2 a, uint32_t e) {
+    double2 r = (e & 1u) ? make_double2(-a.y, a.x) : a;
+    return (e & 2u) ? make_double2(-r.x, -r.y) : r;
+}
+
+__device__ __forceinline__ void bfly_bit(double2 (&v)[kE], int b) {
+#pragma unroll
+    for (int j = 0; j < kE; ++j)
+        if (!((j >> b) & 1)) {
+            const double2 a = v[j], c = v[j | (1 << b)];
+            v[j] = make_double2(a.x + c.x, a.y + c.y);
+            v[j | (1 << b)] = make_double2(a.x - c.x, a.y - c.y);
+        }
+}
+
+__device__ __forceinline__ void bfly(double2 (&v)[kE], uint32_t bm) {
+    if (bm & 1u) bfly_bit(v, 0);
+    if (bm & 2u) bfly_bit(v, 1);
+    if (bm & 4u) bfly_bit(v, 2);
+    if (bm & 8u) bfly_bit(v, 3);
+    if (bm & 16u) bfly_bit(v, 4);
+}
+
+template <typename T, int MODE, bool PREFETCH>
+__global__ void __launch_bounds__(256)
+k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
+       double tau, int halv, double *__restrict__ partial) {
+    extern __shared__ double2 lds[];
+    __shared__ double cks[kMaxPassTerms];
+    __shared__ double red[256];
+    const PassDev &pd = *pdp;
+    const int D = pd.D, TL = D - 5, c = pd.c, m = pd.m, nr = pd.nr, rho = pd.rho;
+    const int L = pd.lam_round;
+    const uint32_t tid = threadIdx.x;
+    const uint8_t *tb = ws + pd.term_off;
+    const uint32_t *zeta = (const uint32_t *)tb;
+    const int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
+    const uint64_t *ztile = (const uint64_t *)(tb + o2);
+    const double *coef = (const double *)(tb + o2 + 8 * (int64_t)m);
+    const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
+    const double scale = pd.scale;
+
+    // ---- per-thread constants (tile independent) ----
+    // scatter/gather: element j of thread t is pivot pattern t + (j << TL)
+    auto pivot_vec = [&](int i) -> uint64_t { return i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]; };
+    uint64_t off_t = 0;
+    uint32_t tc_t = 0;
+    for (int i = 0; i < TL; ++i)
+        if ((tid >> i) & 1) {
+            off_t ^= pivot_vec(i);
+            tc_t ^= pd.mr[i];
+        }
+    const uint32_t sl_t = lds_slot(tc_t);
+    uint64_t pvh[5];
+    uint32_t slh[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        pvh[b] = pivot_vec(TL + b);
+        slh[b] = lds_slot(pd.mr[TL + b]);
+    }
+    // rounds: thread-index bits fill the tile coordinates outside reg[r], lowest first
+    const int nrounds = nr > 0 ? nr : 1;
+    uint32_t base_t[4] = {0, 0, 0, 0}, base_sl[4] = {0, 0, 0, 0}, rs[4][5] = {};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r >= nrounds) break;
+        uint32_t regm = 0;
+        for (int b = 0; b < 5; ++b) regm |= 1u << pd.reg[r][b];
+        uint32_t bt = 0;
+        int i = 0;
+        for (int q = 0; q < D; ++q)
+            if (!((regm >> q) & 1)) {
+                bt |= ((tid >> i) & 1u) << q;
+                ++i;
+            }
+        base_t[r] = bt;
+        base_sl[r] = lds_slot(bt);
+        for (int b = 0; b < 5; ++b) rs[r][b] = lds_slot(1u << pd.reg[r][b]);
+    }
+    // CZ/S phase exponents i^{q(y)} of this thread's 32 amplitudes in chunk 0
+    uint64_t qe = 0;
+    if (nr > 0) {
+        for (int j = 0; j < kE; ++j) {
+            uint32_t t = base_t[0];
+            for (int b = 0; b < 5; ++b)
+                if ((j >> b) & 1) t ^= 1u << pd.reg[0][b];
+            const uint32_t y = t & rmask;
+            uint32_t q = 0;
+            for (int i2 = 0; i2 < rho; ++i2)
+                if ((y >> i2) & 1) q += __popc(pd.B[i2] & y);
+            qe |= (uint64_t)(q & 3u) << (2 * j);
+        }
+    }
+
+    double acc = 0.0;
+    T pre[kE];
+    auto load_tile = [&](int64_t ti, uint64_t &xT_out) {
+        uint64_t xT = 0;
+        for (int i = 0; i < pd.n_free; ++i)
+            if ((ti >> i) & 1) xT |= (uint64_t)1 << pd.free_pos[i];
+        xT_out = xT;
+        uint64_t co = xT ^ off_t;
+#pragma unroll
+        for (int j = 0; j < kE; ++j) {
+            if (j) co ^= pvh[__builtin_ctz(j)];
+            pre[j] = state[co];
+        }
+    };
+    auto to_d2 = [](T a) -> double2 { return make_double2((double)a.x, (double)a.y); };
+
+    int64_t ti = blockIdx.x;
+    uint64_t xT_cur = 0, xT_next = 0;
+    if (PREFETCH && ti < pd.n_tiles) load_tile(ti, xT_cur);
+    for (; ti < pd.n_tiles; ti += gridDim.x) {
+        if (!PREFETCH) load_tile(ti, xT_cur);
+        // scatter the prefetched tile into LDS
+        {
+            uint32_t cs = sl_t;
+            asm volatile("" : "+v"(cs));
+#pragma unroll
+            for (int j = 0; j < kE; ++j) {
+                if (j) cs ^= slh[__builtin_ctz(j)];
+                lds[cs] = to_d2(pre[j]);
+            }
+        }
+        for (int k = tid; k < m; k += blockDim.x) {
+            const double v = coef[k];
+            cks[k] = (__popcll(ztile[k] & xT_cur) & 1) ? -v : v;
+        }
+        const int64_t tn = ti + gridDim.x;
+        if (PREFETCH && tn < pd.n_tiles) load_tile(tn, xT_next);
+        __syncthreads();
+
+        double2 v[kE];
+        // the asm barriers keep the loop-invariant address chains from being
+        // hoisted out of the tile loop (they would stay live in registers)
+        auto rd = [&](int r) {
+            uint32_t cs = base_sl[r];
+            asm volatile("" : "+v"(cs));
+#pragma unroll
+            for (int jj = 0; jj < kE; ++jj) {
+                if (jj) cs ^= rs[r][__builtin_ctz(jj)];
+                v[jj ^ (jj >> 1)] = lds[cs];
+            }
+        };
+        auto wr = [&](int r) {
+            uint32_t cs = base_sl[r];
+            asm volatile("" : "+v"(cs));
+#pragma unroll
+            for (int jj = 0; jj < kE; ++jj) {
+                if (jj) cs ^= rs[r][__builtin_ctz(jj)];
+                lds[cs] = v[jj ^ (jj >> 1)];
+            }
+        };
+        auto lam = [&](int r) {
+            // phi over the 32 register patterns: bucketed coefficients, then a
+            // 32-point Walsh-Hadamard of the bucket sums
+            double A[kE];
+            const uint32_t bb = base_t[r];
+#pragma unroll
+            for (int w = 0; w < kE; ++w) {
+                double sacc = 0.0;
+                for (int k = pd.bucket[w]; k < pd.bucket[w + 1]; ++k) {
+                    const double ck = cks[k];
+                    sacc += (__popc(zeta[k] & bb) & 1) ? -ck : ck;
+                }
+                A[w] = sacc;
+            }
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+#pragma unroll
+                for (int j = 0; j < kE; ++j)
+                    if (!((j >> b) & 1)) {
+                        const double a0 = A[j], a1 = A[j | (1 << b)];
+                        A[j] = a0 + a1;
+                        A[j | (1 << b)] = a0 - a1;
+                    }
+            if (MODE == 0) {
+#pragma unroll
+                for (int j = 0; j < kE; ++j) {
+                    double cc, ss;
+                    cis(-tau * A[j], halv, cc, ss);
+                    cc *= scale;
+                    ss *= scale;
+                    const double2 a = v[j];
+                    v[j] = make_double2(fma(a.x, cc, -a.y * ss), fma(a.x, ss, a.y * cc));
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kE; ++j) acc += (v[j].x * v[j].x + v[j].y * v[j].y) * A[j] * scale;
+            }
+        };
+
+        if (nr == 0) {
+            rd(0);
+            lam(0);
+            if (MODE == 0) wr(0);
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r >= nr) break;
+                rd(r);
+                if (r == 0) {
+#pragma unroll
+                    for (int j = 0; j < kE; ++j) v[j] = rot_ipow(v[j], (uint32_t)(qe >> (2 * j)) & 3u);
+                }
+                bfly(v, pd.bmask[r]);
+                if (r == nr - 1) {
+                    lam(r);
+                    if (MODE == 0) {
+                        bfly(v, pd.bmask[r]);
+                        if (r == 0) {
+#pragma unroll
+                            for (int j = 0; j < kE; ++j)
+                                v[j] = rot_ipow(v[j], (4u - ((uint32_t)(qe >> (2 * j)) & 3u)) & 3u);
+                        }
+                    }
+                }
+                if (MODE == 0 || r < nr - 1) wr(r);
+                __syncthreads();
+            }
+            if (MODE == 0) {
+#pragma unroll
+                for (int r = 2; r >= 0; --r) {
+                    if (r > nr - 2) continue;
+                    rd(r);
+                    bfly(v, pd.bmask[r]);
+                    if (r == 0) {
+#pragma unroll
+                        for (int j = 0; j < kE; ++j)
+                            v[j] = rot_ipow(v[j], (4u - ((uint32_t)(qe >> (2 * j)) & 3u)) & 3u);
+                    }
+                    wr(r);
+                    __syncthreads();
+                }
+            }
+        }
+        if (MODE == 0) {
+            // gather back to HBM
+            uint32_t cs = sl_t;
+            asm volatile("" : "+v"(cs));
+            uint64_t co = xT_cur ^ off_t;
+#pragma unroll
+            for (int j = 0; j < kE; ++j) {
+                if (j) {
+                    cs ^= slh[__builtin_ctz(j)];
+                    co ^= pvh[__builtin_ctz(j)];
+                }
+                st_amp(state, (int64_t)co, lds[cs]);
+            }
+            __syncthreads();
+        }
+        if (PREFETCH) xT_cur = xT_next;
+    }
+    if (MODE == 1) {
+        double s2 = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] += s2;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_norm2(const T *__restrict__ a, int64_t dim, double *__restrict__ partial) {
@@ -277,6 +594,8 @@ static sd_status hip_check(hipError_t e, const char *what) {
 }
 
 static int g_num_cu = 0;
+static bool g_prefetch = true;   // SD_PREFETCH=0 disables the register prefetch
+static bool g_generic = false;   // SD_GENERIC_KERNEL=1 routes every pass to k_pass
 static std::once_flag g_once;
 
 static void init_device_props() {
@@ -284,11 +603,19 @@ static void init_device_props() {
     if (hipGetDevice(&dev) != hipSuccess) return;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) g_num_cu = prop.multiProcessorCount;
+    if (const char *e = std::getenv("SD_PREFETCH")) g_prefetch = std::atoi(e) != 0;
+    if (const char *e = std::getenv("SD_GENERIC_KERNEL")) g_generic = std::atoi(e) != 0;
     const int lds = (1 << kMaxTileLog2) * 16;
     hipFuncSetAttribute((const void *)k_pass<float2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipFuncSetAttribute((const void *)k_pass<float2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipFuncSetAttribute((const void *)k_pass<double2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipFuncSetAttribute((const void *)k_pass<double2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipFuncSetAttribute((const void *)k_tile<float2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipFuncSetAttribute((const void *)k_tile<float2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipFuncSetAttribute((const void *)k_tile<double2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipFuncSetAttribute((const void *)k_tile<double2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipFuncSetAttribute((const void *)k_tile<float2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipFuncSetAttribute((const void *)k_tile<double2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 static int grid_for(int64_t tiles) {
@@ -310,6 +637,25 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
     if (ph.D > kMaxTileLog2 || (int)ph.terms.size() > kMaxPassTerms)
         return fail(SD_ERR_INTERNAL, "pass exceeds the on-chip tile limits");
     const size_t lds = (size_t)16 << ph.D;
+    if (ph.D >= kTileMinD && !g_generic) {
+        int halv = 0;
+        const double th = std::fabs(tau) * ph.coef_abs_sum;
+        while (halv < 60 && std::ldexp(th, -halv) > 0.25) ++halv;
+        const int threads = 1 << (ph.D - 5);
+        // tiles of 2^13 fill one CU's LDS: one block per CU, next tile
+        // prefetched into registers; smaller tiles run two or more blocks per CU
+        const bool pf = MODE == 0 && ph.D >= 13 && g_prefetch;
+        const int per_cu = ph.D >= 13 ? 1 : 2;
+        const int g2 = MODE == 1 ? grid
+                                 : (int)std::min<int64_t>(tiles, (int64_t)std::max(1, g_num_cu) * per_cu);
+        if (pf)
+            hipLaunchKernelGGL((k_tile<T, MODE, true>), dim3(g2), dim3(threads), lds, s, (T *)state,
+                               pd, ws, tau, halv, partial);
+        else
+            hipLaunchKernelGGL((k_tile<T, MODE, false>), dim3(g2), dim3(threads), lds, s, (T *)state,
+                               pd, ws, tau, halv, partial);
+        return hip_check(hipGetLastError(), "k_tile launch");
+    }
     hipLaunchKernelGGL((k_pass<T, MODE>), dim3(grid), dim3(kBlock), lds, s, (T *)state, pd, ws,
                        tau, partial);
     return hip_check(hipGetLastError(), "k_pass launch");

@@ -21,6 +21,13 @@ struct alignas(256) PassDev {
     uint32_t mr[kMaxD];     // tile coordinates of each pivot vector
     uint32_t B[kMaxD];      // CZ/S quadratic form rows (rho used)
     uint8_t free_pos[64];   // physical bit of each tile-index bit
+    // register-round schedule (k_tile)
+    int32_t nr;             // Walsh-Hadamard chunks of <= 5 span coordinates
+    int32_t lam_round;      // chunk whose round applies Lambda
+    uint8_t reg[4][8];      // tile coordinates in registers per chunk (5 used)
+    uint32_t bmask[4];      // register slots that get butterflies per chunk
+    int32_t bucket[33];     // term offsets by Lambda pattern on reg[lam_round]
+    double coef_abs_sum;    // sum |coef| of the pass
 };
 
 // term arrays at term_off: uint32 zeta[m]; (pad to 8) uint64 ztile[m]; double coef[m]

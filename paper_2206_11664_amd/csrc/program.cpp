@@ -46,6 +46,76 @@ struct Coords {
     }
 };
 
+// Register-round schedule for the on-chip transform of a tile with D
+// coordinates (span coordinates 0..rho-1, spectators rho..D-1).  A thread
+// holds 32 amplitudes: the 5 tile coordinates of the current round vary over
+// them, the remaining D-5 coordinates are the thread index (lowest first, so
+// consecutive lanes touch consecutive on-chip slots).  Span coordinates are
+// taken five at a time; a short last chunk is filled with the highest other
+// coordinates, which are carried without butterflies.  Lambda is applied in
+// the round of the last chunk, between the two transforms.
+sd_status plan_rounds(PassHost *ps) {
+    PassHost &p = *ps;
+    const int D = p.D, rho = p.rho;
+    p.nr = 0;
+    if (D < 5) {  // tiny tile: handled by the generic kernel only
+        p.lam_round = 0;
+    } else {
+        auto fill = [&](int r, std::vector<int> bits, uint32_t bm) {
+            for (int b = D - 1; (int)bits.size() < 5 && b >= 0; --b)
+                if (std::find(bits.begin(), bits.end(), b) == bits.end()) bits.push_back(b);
+            for (int i = 0; i < 5; ++i) p.reg[r][i] = (uint8_t)bits[i];
+            p.bmask[r] = bm;
+        };
+        if (rho == 0) {
+            fill(0, {}, 0u);
+            p.lam_round = 0;
+        } else {
+            p.nr = (rho + 4) / 5;
+            if (p.nr > 4) return fail(SD_ERR_INTERNAL, "too many register rounds");
+            for (int r = 0; r < p.nr; ++r) {
+                std::vector<int> bits;
+                for (int b = 5 * r; b < std::min(rho, 5 * r + 5); ++b) bits.push_back(b);
+                fill(r, bits, (1u << bits.size()) - 1);
+            }
+            p.lam_round = p.nr - 1;
+        }
+    }
+    // sort the Lambda terms by their pattern on the Lambda round's registers
+    const int L = p.lam_round;
+    auto pattern = [&](uint32_t z) {
+        uint32_t w = 0;
+        if (D >= 5)
+            for (int i = 0; i < 5; ++i) w |= ((z >> p.reg[L][i]) & 1u) << i;
+        return w;
+    };
+    const size_t m = p.zeta.size();
+    std::vector<size_t> idx(m);
+    for (size_t i = 0; i < m; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](size_t a, size_t b) { return pattern(p.zeta[a]) < pattern(p.zeta[b]); });
+    std::vector<int64_t> t2;
+    std::vector<uint32_t> z2;
+    std::vector<uint64_t> zt2;
+    std::vector<double> c2;
+    for (size_t i : idx) {
+        t2.push_back(p.terms[i]);
+        z2.push_back(p.zeta[i]);
+        zt2.push_back(p.ztile[i]);
+        c2.push_back(p.coef[i]);
+    }
+    p.terms.swap(t2);
+    p.zeta.swap(z2);
+    p.ztile.swap(zt2);
+    p.coef.swap(c2);
+    p.bucket.assign(33, 0);
+    for (size_t i = 0; i < m; ++i) p.bucket[pattern(p.zeta[i]) + 1]++;
+    for (int w = 0; w < 32; ++w) p.bucket[w + 1] += p.bucket[w];
+    p.coef_abs_sum = 0;
+    for (double c : p.coef) p.coef_abs_sum += std::fabs(c);
+    return SD_OK;
+}
+
 sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
                      const std::vector<int64_t> &ids, int D_target, int c_req,
                      PassHost *ps) {
@@ -182,7 +252,7 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
         double s = (sr.sign[i] ? -1.0 : 1.0) * (ephase[i] == 2 ? -1.0 : 1.0);
         p.coef.push_back(T[k].c * s);
     }
-    return SD_OK;
+    return plan_rounds(&p);
 }
 
 }  // namespace

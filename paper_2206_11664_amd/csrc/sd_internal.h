@@ -121,6 +121,14 @@ struct PassHost {
     std::vector<uint32_t> zeta;     // per term, D-bit mask of Lambda
     std::vector<uint64_t> ztile;    // per term, physical z for the tile sign
     std::vector<double> coef;       // per term, c_k (-1)^{r_k} i^{e_k}
+    double coef_abs_sum = 0;        // sum |c_k| (bounds the phase angle)
+    // register-round schedule of the on-chip Walsh-Hadamard (see device.hip)
+    int nr = 0;                     // chunks of <= 5 span coordinates
+    uint8_t reg[4][5] = {};         // tile coordinates held in registers per chunk
+    uint32_t bmask[4] = {};         // which of the 5 register slots are butterflied
+    int lam_round = 0;              // chunk whose round applies Lambda
+    std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
+                                    // pattern on the registers of lam_round
 };
 
 struct Program {
