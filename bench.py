@@ -34,6 +34,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reference-modes", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -139,10 +140,33 @@ def main():
                                  "energy_drift_c64": e64 - e0, "energy_drift_c128": e128 - e0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "k_pass<float2,0>",
+                     "kernel": "k_tile<float2,0,true>",
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "bytes_per_launch": bytes_per_launch},
     }
+
+    if not args.no_reference_modes:
+        # the paper's own comparison on this GPU: term-by-term rotations (its
+        # baseline) and its circuit applied layer by layer, one step each, c64
+        ref = {}
+        for name, mode in (("termwise", sd.SD_MODE_TERMWISE), ("paper_layers", sd.SD_MODE_PAPER_LAYERS)):
+            log(f"reference mode {name}")
+            o = sd.sd_plan_options_default()
+            o.mode = mode
+            rp = sd.Plan(n, m.paulis, m.coeffs, o).bind("cuda")
+            a = d128_0.to(torch.complex64)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            rp.evolve(a, m.dt, 1, 1)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            sec = ev0.elapsed_time(ev1) / 1e3
+            ref[name + "_steps_per_s"] = round(1.0 / sec, 5)
+            ref["tiles_speedup_vs_" + name] = round(sps64 * sec, 2)
+            del a, rp
+        ref["termwise_passes_per_step"] = int(info.n_terms)
+        result["paper_comparison_c64"] = ref
 
     if not args.no_cpu_baseline:
         import oracle

@@ -109,7 +109,17 @@ typedef struct {
        cache lines; 0 = default (4 for c64 = 128 B, 3 for c128 = 128 B). */
     int32_t coalesce_log2_c64;
     int32_t coalesce_log2_c128;
+    /* Execution mode of sd_evolve (sd_expectation always uses the tiles):
+       SD_MODE_TILES (default): one fused tile pass per commuting sub-group;
+       SD_MODE_PAPER_LAYERS: the paper's circuit layer by layer, one HBM pass
+         per H gate, per CNOT control (its fan-out applied at once), for all
+         S+CZ, and for Lambda (Sec. "Implementations");
+       SD_MODE_TERMWISE: one Pauli-rotation pass per term (Eq. trotter_decomp,
+         the paper's baseline), in the same group order. */
+    int32_t mode;
 } sd_plan_options;
+
+enum { SD_MODE_TILES = 0, SD_MODE_PAPER_LAYERS = 1, SD_MODE_TERMWISE = 2 };
 
 /* Fill `opt` with the defaults. */
 void sd_plan_options_default(sd_plan_options *opt);

@@ -59,7 +59,7 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         d.nr = p.nr;
         d.lam_round = p.lam_round;
         for (int r = 0; r < 4; ++r) {
-            for (int b = 0; b < 5; ++b) d.reg[r][b] = p.reg[r][b];
+            for (int b = 0; b < 8; ++b) d.reg[r][b] = p.reg[r][b];
             d.bmask[r] = p.bmask[r];
         }
         for (int w = 0; w < 33; ++w) d.bucket[w] = p.bucket.empty() ? 0 : p.bucket[w];
@@ -228,16 +228,20 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
 // ---------------------------------------------------------------------------
 // k_tile: register-round tile pass (tiles of 2^D amplitudes, D >= kTileMinD)
 // ---------------------------------------------------------------------------
-// A block of 2^(D-5) threads owns one tile at a time; every thread holds 32
-// amplitudes in FP64 registers.  In the round of chunk r the 32 amplitudes of
-// a thread differ in the 5 tile coordinates reg[r] and share the others
-// (taken from the thread index), so the butterflies of those coordinates run
-// in registers; between rounds the tile is exchanged through LDS.  The LDS
-// slot of tile coordinate t is t ^ fold(t >> 3), fold = XOR of its 3-bit
-// groups: whenever the three lowest thread-index bits address three adjacent
-// coordinates, the 8 lanes of a 128-byte LDS phase land in distinct banks.
-constexpr int kE = 32;
+// A block of 2^(D-kLE) threads owns one tile at a time; every thread holds
+// kE = 2^kLE amplitudes in FP64 registers.  In the round of chunk r the kE
+// amplitudes of a thread differ in the kLE tile coordinates reg[r] and share
+// the others (taken from the thread index), so the butterflies of those
+// coordinates run in registers; between rounds the tile is exchanged through
+// LDS.  The LDS slot of tile coordinate t is t ^ fold(t >> 3) (fold = XOR of
+// its 3-bit groups): whenever the three lowest thread-index bits address three
+// adjacent coordinates, the 8 lanes of a 128-byte LDS phase hit distinct banks.
+// Rounds run in a loop over a runtime chunk index so that each routine exists
+// once in the code object.
+constexpr int kLE = 4;
+constexpr int kE = 1 << kLE;
 constexpr int kTileMinD = 10;
+constexpr int kMaxThreads = 1 << (kMaxTileLog2 - kLE);
 
 __device__ __forceinline__ uint32_t lds_slot(uint32_t t) {
     uint32_t h = t >> 3;
@@ -271,75 +275,103 @@ __device__ __forceinline__ void cis(double th, int halv, double &c, double &s) {
     }
 }
 
-// a * i^e, e in 0..3
-__device__ __forceinline__ double2 rot_ipow(double2 a, uint32_t e) {
-    double2 r = (e & 1u) ? make_double2(-a.y, a.x) : a;
-    return (e & 2u) ? make_double2(-r.x, -r.y) : r;
+// (re, im) * i^e, e in 0..3
+__device__ __forceinline__ void rot_ipow(double &re, double &im, uint32_t e) {
+    const double a = re, b = im;
+    re = (e & 1u) ? -b : a;
+    im = (e & 1u) ? a : b;
+    if (e & 2u) {
+        re = -re;
+        im = -im;
+    }
 }
 
-__device__ __forceinline__ void bfly_bit(double2 (&v)[kE], int b) {
+__device__ __forceinline__ void bfly(double (&re)[kE], double (&im)[kE], uint32_t bm) {
 #pragma unroll
-    for (int j = 0; j < kE; ++j)
-        if (!((j >> b) & 1)) {
-            const double2 a = v[j], c = v[j | (1 << b)];
-            v[j] = make_double2(a.x + c.x, a.y + c.y);
-            v[j | (1 << b)] = make_double2(a.x - c.x, a.y - c.y);
-        }
+    for (int b = 0; b < kLE; ++b) {
+        if (!((bm >> b) & 1u)) continue;
+#pragma unroll
+        for (int j = 0; j < kE; ++j)
+            if (!((j >> b) & 1)) {
+                const int k = j | (1 << b);
+                const double ar = re[j], ai = im[j], cr = re[k], ci = im[k];
+                re[j] = ar + cr;
+                im[j] = ai + ci;
+                re[k] = ar - cr;
+                im[k] = ai - ci;
+            }
+    }
 }
 
-__device__ __forceinline__ void bfly(double2 (&v)[kE], uint32_t bm) {
-    if (bm & 1u) bfly_bit(v, 0);
-    if (bm & 2u) bfly_bit(v, 1);
-    if (bm & 4u) bfly_bit(v, 2);
-    if (bm & 8u) bfly_bit(v, 3);
-    if (bm & 16u) bfly_bit(v, 4);
-}
-
+// One tile pass over tiles t0, t0 + stride, ... < t1 of the pass `pdp` (the
+// whole pass when called with blockIdx.x, n_tiles, gridDim.x).  MODE 1 adds
+// this block's share of <psi|H_pass|psi> to acc.
 template <typename T, int MODE, bool PREFETCH>
-__global__ void __launch_bounds__(256)
-k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
-       double tau, int halv, double *__restrict__ partial) {
+__device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *__restrict__ pdp,
+                                          const uint8_t *__restrict__ ws, double tau, int64_t t0,
+                                          int64_t t1, int64_t stride, double &acc) {
+    // dynamic LDS: the tile (16 B per amplitude), then the per-thread round bases
     extern __shared__ double2 lds[];
+    uint32_t *thr_base = (uint32_t *)(lds + ((size_t)1 << pdp->D));
+    // the pass's term arrays live in LDS for the whole launch: reading them from
+    // global memory inside the tile loop would make every such read wait for
+    // all outstanding state loads and stores (one counter covers both)
     __shared__ double cks[kMaxPassTerms];
-    __shared__ double red[256];
+    __shared__ double coef[kMaxPassTerms];
+    __shared__ uint64_t ztile[kMaxPassTerms];
+    __shared__ uint32_t zeta[kMaxPassTerms];
+    // per-round uniform data, staged so that no byte-sized pass field is read
+    // from global memory inside the tile loop (such reads are vector loads)
+    __shared__ uint32_t s_rs[4][kLE];
+    __shared__ uint32_t s_free[64];
+    __syncthreads();  // a previous call of this block may still read the arrays
     const PassDev &pd = *pdp;
-    const int D = pd.D, TL = D - 5, c = pd.c, m = pd.m, nr = pd.nr, rho = pd.rho;
-    const int L = pd.lam_round;
+    int halv = 0;
+    if (MODE == 0) {
+        const double th = fabs(tau) * pd.coef_abs_sum;
+        while (halv < 60 && ldexp(th, -halv) > 0.25) ++halv;
+    }
+    const int D = pd.D, TL = D - kLE, c = pd.c, m = pd.m, nr = pd.nr, rho = pd.rho;
     const uint32_t tid = threadIdx.x;
-    const uint8_t *tb = ws + pd.term_off;
-    const uint32_t *zeta = (const uint32_t *)tb;
-    const int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
-    const uint64_t *ztile = (const uint64_t *)(tb + o2);
-    const double *coef = (const double *)(tb + o2 + 8 * (int64_t)m);
+    const int n_free = pd.n_free;
+    if (tid < 4 * kLE) s_rs[tid / kLE][tid % kLE] = lds_slot(1u << pd.reg[tid / kLE][tid % kLE]);
+    if (tid < 64) s_free[tid] = pd.free_pos[tid];
+    {
+        const uint8_t *tb = ws + pd.term_off;
+        const int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
+        for (int k = tid; k < m; k += blockDim.x) {
+            zeta[k] = ((const uint32_t *)tb)[k];
+            ztile[k] = ((const uint64_t *)(tb + o2))[k];
+            coef[k] = ((const double *)(tb + o2 + 8 * (int64_t)m))[k];
+        }
+    }
     const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
     const double scale = pd.scale;
+    const int nrounds = nr > 0 ? nr : 1;
 
     // ---- per-thread constants (tile independent) ----
     // scatter/gather: element j of thread t is pivot pattern t + (j << TL)
-    auto pivot_vec = [&](int i) -> uint64_t { return i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]; };
     uint64_t off_t = 0;
     uint32_t tc_t = 0;
     for (int i = 0; i < TL; ++i)
         if ((tid >> i) & 1) {
-            off_t ^= pivot_vec(i);
+            off_t ^= i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c];
             tc_t ^= pd.mr[i];
         }
     const uint32_t sl_t = lds_slot(tc_t);
-    uint64_t pvh[5];
-    uint32_t slh[5];
+    // uniform increments of the Gray-code address walks over the kE elements
+    uint64_t pv[kLE];
+    uint32_t sv[kLE];
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-        pvh[b] = pivot_vec(TL + b);
-        slh[b] = lds_slot(pd.mr[TL + b]);
+    for (int b = 0; b < kLE; ++b) {
+        const int i = TL + b;
+        pv[b] = i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c];
+        sv[b] = lds_slot(pd.mr[i]);
     }
     // rounds: thread-index bits fill the tile coordinates outside reg[r], lowest first
-    const int nrounds = nr > 0 ? nr : 1;
-    uint32_t base_t[4] = {0, 0, 0, 0}, base_sl[4] = {0, 0, 0, 0}, rs[4][5] = {};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        if (r >= nrounds) break;
+    for (int r = 0; r < nrounds; ++r) {
         uint32_t regm = 0;
-        for (int b = 0; b < 5; ++b) regm |= 1u << pd.reg[r][b];
+        for (int b = 0; b < kLE; ++b) regm |= 1u << pd.reg[r][b];
         uint32_t bt = 0;
         int i = 0;
         for (int q = 0; q < D; ++q)
@@ -347,189 +379,251 @@ k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
                 bt |= ((tid >> i) & 1u) << q;
                 ++i;
             }
-        base_t[r] = bt;
-        base_sl[r] = lds_slot(bt);
-        for (int b = 0; b < 5; ++b) rs[r][b] = lds_slot(1u << pd.reg[r][b]);
+        thr_base[r * blockDim.x + tid] = bt;
     }
-    // CZ/S phase exponents i^{q(y)} of this thread's 32 amplitudes in chunk 0
-    uint64_t qe = 0;
+    // CZ/S phase exponents i^{q(y)} of this thread's amplitudes in chunk 0
+    uint32_t qe = 0;
     if (nr > 0) {
+        const uint32_t b0 = thr_base[tid];
         for (int j = 0; j < kE; ++j) {
-            uint32_t t = base_t[0];
-            for (int b = 0; b < 5; ++b)
+            uint32_t t = b0;
+            for (int b = 0; b < kLE; ++b)
                 if ((j >> b) & 1) t ^= 1u << pd.reg[0][b];
             const uint32_t y = t & rmask;
             uint32_t q = 0;
             for (int i2 = 0; i2 < rho; ++i2)
                 if ((y >> i2) & 1) q += __popc(pd.B[i2] & y);
-            qe |= (uint64_t)(q & 3u) << (2 * j);
+            qe |= (q & 3u) << (2 * j);
         }
     }
 
-    double acc = 0.0;
     T pre[kE];
-    auto load_tile = [&](int64_t ti, uint64_t &xT_out) {
+    auto tile_base = [&](int64_t ti) {
         uint64_t xT = 0;
-        for (int i = 0; i < pd.n_free; ++i)
-            if ((ti >> i) & 1) xT |= (uint64_t)1 << pd.free_pos[i];
-        xT_out = xT;
+        for (int i = 0; i < n_free; ++i)
+            if ((ti >> i) & 1) xT |= (uint64_t)1 << s_free[i];
+        return xT;
+    };
+    auto load_tile = [&](uint64_t xT) {
         uint64_t co = xT ^ off_t;
+        asm volatile("" : "+v"(co));
 #pragma unroll
         for (int j = 0; j < kE; ++j) {
-            if (j) co ^= pvh[__builtin_ctz(j)];
+            if (j) co ^= pv[__builtin_ctz(j)];
             pre[j] = state[co];
         }
     };
-    auto to_d2 = [](T a) -> double2 { return make_double2((double)a.x, (double)a.y); };
+    __syncthreads();
 
-    int64_t ti = blockIdx.x;
-    uint64_t xT_cur = 0, xT_next = 0;
-    if (PREFETCH && ti < pd.n_tiles) load_tile(ti, xT_cur);
-    for (; ti < pd.n_tiles; ti += gridDim.x) {
-        if (!PREFETCH) load_tile(ti, xT_cur);
-        // scatter the prefetched tile into LDS
-        {
-            uint32_t cs = sl_t;
-            asm volatile("" : "+v"(cs));
+    auto scatter = [&]() {
+        uint32_t cs = sl_t;
+        asm volatile("" : "+v"(cs));
 #pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                if (j) cs ^= slh[__builtin_ctz(j)];
-                lds[cs] = to_d2(pre[j]);
-            }
+        for (int j = 0; j < kE; ++j) {
+            if (j) cs ^= sv[__builtin_ctz(j)];
+            lds[cs] = make_double2((double)pre[j].x, (double)pre[j].y);
         }
+    };
+    auto signs = [&](uint64_t xT) {
         for (int k = tid; k < m; k += blockDim.x) {
             const double v = coef[k];
-            cks[k] = (__popcll(ztile[k] & xT_cur) & 1) ? -v : v;
+            cks[k] = (__popcll(ztile[k] & xT) & 1) ? -v : v;
         }
-        const int64_t tn = ti + gridDim.x;
-        if (PREFETCH && tn < pd.n_tiles) load_tile(tn, xT_next);
-        __syncthreads();
-
-        double2 v[kE];
-        // the asm barriers keep the loop-invariant address chains from being
-        // hoisted out of the tile loop (they would stay live in registers)
-        auto rd = [&](int r) {
-            uint32_t cs = base_sl[r];
-            asm volatile("" : "+v"(cs));
+    };
+    auto transform = [&]() {
+        double re[kE], im[kE];
+        const int total = nr > 0 ? 2 * nr - 1 : 1;
+        for (int step = 0; step < total; ++step) {
+            const int r = step < nrounds ? step : 2 * nr - 2 - step;
+            const bool lam_round = step == nrounds - 1;
+            const uint32_t base = thr_base[r * blockDim.x + tid];
+            uint32_t rs[kLE];
 #pragma unroll
-            for (int jj = 0; jj < kE; ++jj) {
-                if (jj) cs ^= rs[r][__builtin_ctz(jj)];
-                v[jj ^ (jj >> 1)] = lds[cs];
-            }
-        };
-        auto wr = [&](int r) {
-            uint32_t cs = base_sl[r];
-            asm volatile("" : "+v"(cs));
+            for (int b = 0; b < kLE; ++b) rs[b] = s_rs[r][b];
+            {
+                uint32_t cs = lds_slot(base);
 #pragma unroll
-            for (int jj = 0; jj < kE; ++jj) {
-                if (jj) cs ^= rs[r][__builtin_ctz(jj)];
-                lds[cs] = v[jj ^ (jj >> 1)];
-            }
-        };
-        auto lam = [&](int r) {
-            // phi over the 32 register patterns: bucketed coefficients, then a
-            // 32-point Walsh-Hadamard of the bucket sums
-            double A[kE];
-            const uint32_t bb = base_t[r];
-#pragma unroll
-            for (int w = 0; w < kE; ++w) {
-                double sacc = 0.0;
-                for (int k = pd.bucket[w]; k < pd.bucket[w + 1]; ++k) {
-                    const double ck = cks[k];
-                    sacc += (__popc(zeta[k] & bb) & 1) ? -ck : ck;
+                for (int jj = 0; jj < kE; ++jj) {
+                    if (jj) cs ^= rs[__builtin_ctz(jj)];
+                    const double2 a = lds[cs];
+                    re[jj ^ (jj >> 1)] = a.x;
+                    im[jj ^ (jj >> 1)] = a.y;
                 }
-                A[w] = sacc;
             }
+            if (step == 0 && nr > 0) {
 #pragma unroll
-            for (int b = 0; b < 5; ++b)
+                for (int j = 0; j < kE; ++j) rot_ipow(re[j], im[j], (qe >> (2 * j)) & 3u);
+            }
+            const uint32_t bm = pd.bmask[r];
+            bfly(re, im, bm);
+            if (lam_round) {
+                // phi over the kE register patterns: bucket sums of the signed
+                // coefficients, then a kE-point Walsh-Hadamard of the sums
+                double A[kE];
 #pragma unroll
-                for (int j = 0; j < kE; ++j)
-                    if (!((j >> b) & 1)) {
-                        const double a0 = A[j], a1 = A[j | (1 << b)];
-                        A[j] = a0 + a1;
-                        A[j | (1 << b)] = a0 - a1;
+                for (int w = 0; w < kE; ++w) {
+                    double sacc = 0.0;
+                    const int k1 = pd.bucket[w + 1];
+                    for (int k = pd.bucket[w]; k < k1; ++k) {
+                        const double ck = cks[k];
+                        sacc += (__popc(zeta[k] & base) & 1) ? -ck : ck;
                     }
-            if (MODE == 0) {
-#pragma unroll
-                for (int j = 0; j < kE; ++j) {
-                    double cc, ss;
-                    cis(-tau * A[j], halv, cc, ss);
-                    cc *= scale;
-                    ss *= scale;
-                    const double2 a = v[j];
-                    v[j] = make_double2(fma(a.x, cc, -a.y * ss), fma(a.x, ss, a.y * cc));
+                    A[w] = sacc;
                 }
-            } else {
 #pragma unroll
-                for (int j = 0; j < kE; ++j) acc += (v[j].x * v[j].x + v[j].y * v[j].y) * A[j] * scale;
-            }
-        };
-
-        if (nr == 0) {
-            rd(0);
-            lam(0);
-            if (MODE == 0) wr(0);
-            __syncthreads();
-        } else {
+                for (int b = 0; b < kLE; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (r >= nr) break;
-                rd(r);
-                if (r == 0) {
-#pragma unroll
-                    for (int j = 0; j < kE; ++j) v[j] = rot_ipow(v[j], (uint32_t)(qe >> (2 * j)) & 3u);
-                }
-                bfly(v, pd.bmask[r]);
-                if (r == nr - 1) {
-                    lam(r);
-                    if (MODE == 0) {
-                        bfly(v, pd.bmask[r]);
-                        if (r == 0) {
-#pragma unroll
-                            for (int j = 0; j < kE; ++j)
-                                v[j] = rot_ipow(v[j], (4u - ((uint32_t)(qe >> (2 * j)) & 3u)) & 3u);
+                    for (int j = 0; j < kE; ++j)
+                        if (!((j >> b) & 1)) {
+                            const double a0 = A[j], a1 = A[j | (1 << b)];
+                            A[j] = a0 + a1;
+                            A[j | (1 << b)] = a0 - a1;
                         }
+                if (MODE == 0) {
+#pragma unroll
+                    for (int j = 0; j < kE; ++j) {
+                        double cc, ss;
+                        cis(-tau * A[j], halv, cc, ss);
+                        cc *= scale;
+                        ss *= scale;
+                        const double ar = re[j], ai = im[j];
+                        re[j] = fma(ar, cc, -ai * ss);
+                        im[j] = fma(ar, ss, ai * cc);
                     }
+                    bfly(re, im, bm);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kE; ++j) acc += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
                 }
-                if (MODE == 0 || r < nr - 1) wr(r);
+            }
+            if (MODE == 1 && lam_round) break;
+            if (step == total - 1 && nr > 0) {
+#pragma unroll
+                for (int j = 0; j < kE; ++j) rot_ipow(re[j], im[j], (4u - ((qe >> (2 * j)) & 3u)) & 3u);
+            }
+            {
+                uint32_t cs = lds_slot(base);
+                asm volatile("" : "+v"(cs));
+#pragma unroll
+                for (int jj = 0; jj < kE; ++jj) {
+                    if (jj) cs ^= rs[__builtin_ctz(jj)];
+                    lds[cs] = make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]);
+                }
+            }
+            __syncthreads();
+        }
+    };
+    auto gather = [&](uint64_t xT) {
+        uint32_t cs = sl_t;
+        uint64_t co = xT ^ off_t;
+        asm volatile("" : "+v"(cs), "+v"(co));
+#pragma unroll
+        for (int j = 0; j < kE; ++j) {
+            if (j) {
+                cs ^= sv[__builtin_ctz(j)];
+                co ^= pv[__builtin_ctz(j)];
+            }
+            st_amp(state, (int64_t)co, lds[cs]);
+        }
+    };
+
+    int64_t ti = t0;
+    if (PREFETCH) {
+        // Software pipeline.  The loop is rotated so that on every path into
+        // the loop only the next tile's loads are outstanding; inside the body
+        // the stores of the current tile are issued after them, so the wait
+        // for the next tile's data before its scatter does not wait for the
+        // stores (one counter tracks both, in issue order).
+        if (ti < t1) {
+            uint64_t xT_cur = tile_base(ti);
+            load_tile(xT_cur);
+            scatter();
+            signs(xT_cur);
+            int64_t tn = ti + stride;
+            uint64_t xT_next = 0;
+            if (tn < t1) {
+                xT_next = tile_base(tn);
+                load_tile(xT_next);
+            }
+            __syncthreads();
+            while (true) {
+                transform();
+                if (MODE == 0) gather(xT_cur);
+                __syncthreads();
+                if (tn >= t1) break;
+                xT_cur = xT_next;
+                scatter();
+                signs(xT_cur);
+                tn += stride;
+                if (tn < t1) {
+                    xT_next = tile_base(tn);
+                    load_tile(xT_next);
+                }
                 __syncthreads();
             }
-            if (MODE == 0) {
-#pragma unroll
-                for (int r = 2; r >= 0; --r) {
-                    if (r > nr - 2) continue;
-                    rd(r);
-                    bfly(v, pd.bmask[r]);
-                    if (r == 0) {
-#pragma unroll
-                        for (int j = 0; j < kE; ++j)
-                            v[j] = rot_ipow(v[j], (4u - ((uint32_t)(qe >> (2 * j)) & 3u)) & 3u);
-                    }
-                    wr(r);
-                    __syncthreads();
-                }
-            }
         }
-        if (MODE == 0) {
-            // gather back to HBM
-            uint32_t cs = sl_t;
-            asm volatile("" : "+v"(cs));
-            uint64_t co = xT_cur ^ off_t;
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                if (j) {
-                    cs ^= slh[__builtin_ctz(j)];
-                    co ^= pvh[__builtin_ctz(j)];
-                }
-                st_amp(state, (int64_t)co, lds[cs]);
-            }
+    } else {
+        for (; ti < t1; ti += stride) {
+            const uint64_t xT_cur = tile_base(ti);
+            load_tile(xT_cur);
+            scatter();
+            signs(xT_cur);
+            __syncthreads();
+            transform();
+            if (MODE == 0) gather(xT_cur);
             __syncthreads();
         }
-        if (PREFETCH) xT_cur = xT_next;
     }
+}
+
+// block sum in a fixed order: wave sums, then one value per wave through LDS
+__device__ __forceinline__ double block_sum_waves(double acc) {
+    __shared__ double red[kMaxThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    double s2 = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s2 += red[w];
+    return s2;
+}
+
+template <typename T, int MODE, bool PREFETCH>
+__global__ void __launch_bounds__(kMaxThreads)
+k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
+       double tau, double *__restrict__ partial) {
+    double acc = 0.0;
+    tile_pass<T, MODE, PREFETCH>(state, pdp, ws, tau, blockIdx.x, pdp->n_tiles, gridDim.x, acc);
     if (MODE == 1) {
-        double s2 = block_sum(acc, red);
+        const double s2 = block_sum_waves(acc);
         if (threadIdx.x == 0) partial[blockIdx.x] += s2;
+    }
+}
+
+// Ensemble level launch: segment i is one pass of one instance (its tiles are
+// items first_item .. first_item + n_tiles - 1 of a flat list); every block
+// takes a contiguous share of the items, so it changes instance rarely.
+struct MultiSeg {
+    void *state;
+    const PassDev *pd;
+    const uint8_t *ws;
+    double tau;
+    int64_t first_item;
+    int64_t n_tiles;
+};
+
+template <typename T, bool PREFETCH>
+__global__ void __launch_bounds__(kMaxThreads)
+k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
+    const int64_t lo = (total * (int64_t)blockIdx.x) / gridDim.x;
+    const int64_t hi = (total * (int64_t)(blockIdx.x + 1)) / gridDim.x;
+    double acc = 0.0;
+    for (int i = 0; i < nseg; ++i) {
+        const MultiSeg sg = segs[i];
+        const int64_t a = sg.first_item, b = sg.first_item + sg.n_tiles;
+        const int64_t s0 = a > lo ? a : lo, s1 = b < hi ? b : hi;
+        if (s0 >= s1) continue;
+        tile_pass<T, 0, PREFETCH>((T *)sg.state, sg.pd, sg.ws, sg.tau, s0 - a, s1 - a, 1, acc);
     }
 }
 
@@ -594,7 +688,7 @@ static sd_status hip_check(hipError_t e, const char *what) {
 }
 
 static int g_num_cu = 0;
-static bool g_prefetch = true;   // SD_PREFETCH=0 disables the register prefetch
+static bool g_prefetch = true;   // SD_PREFETCH=0 disables the software pipeline
 static bool g_generic = false;   // SD_GENERIC_KERNEL=1 routes every pass to k_pass
 static std::once_flag g_once;
 
@@ -605,17 +699,21 @@ static void init_device_props() {
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) g_num_cu = prop.multiProcessorCount;
     if (const char *e = std::getenv("SD_PREFETCH")) g_prefetch = std::atoi(e) != 0;
     if (const char *e = std::getenv("SD_GENERIC_KERNEL")) g_generic = std::atoi(e) != 0;
-    const int lds = (1 << kMaxTileLog2) * 16;
-    hipFuncSetAttribute((const void *)k_pass<float2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_pass<float2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_pass<double2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_pass<double2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_tile<float2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_tile<float2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_tile<double2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_tile<double2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_tile<float2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipFuncSetAttribute((const void *)k_tile<double2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const int lds = (1 << kMaxTileLog2) * 16 + 4 * 4 * kMaxThreads;
+    (void)hipFuncSetAttribute((const void *)k_pass<float2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_pass<float2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_pass<double2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_pass<double2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<float2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<float2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<double2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<double2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<float2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<double2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<float2, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile<double2, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile_multi<float2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_tile_multi<double2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 static int grid_for(int64_t tiles) {
@@ -637,23 +735,22 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
     if (ph.D > kMaxTileLog2 || (int)ph.terms.size() > kMaxPassTerms)
         return fail(SD_ERR_INTERNAL, "pass exceeds the on-chip tile limits");
     const size_t lds = (size_t)16 << ph.D;
+    static_assert(kLE == kRegBits, "register round width mismatch");
     if (ph.D >= kTileMinD && !g_generic) {
-        int halv = 0;
-        const double th = std::fabs(tau) * ph.coef_abs_sum;
-        while (halv < 60 && std::ldexp(th, -halv) > 0.25) ++halv;
-        const int threads = 1 << (ph.D - 5);
+        const int threads = 1 << (ph.D - kLE);
         // tiles of 2^13 fill one CU's LDS: one block per CU, next tile
         // prefetched into registers; smaller tiles run two or more blocks per CU
-        const bool pf = MODE == 0 && ph.D >= 13 && g_prefetch;
+        const bool pf = g_prefetch;
         const int per_cu = ph.D >= 13 ? 1 : 2;
+        const size_t lds_tile = lds + (size_t)4 * 4 * threads;
         const int g2 = MODE == 1 ? grid
                                  : (int)std::min<int64_t>(tiles, (int64_t)std::max(1, g_num_cu) * per_cu);
         if (pf)
-            hipLaunchKernelGGL((k_tile<T, MODE, true>), dim3(g2), dim3(threads), lds, s, (T *)state,
-                               pd, ws, tau, halv, partial);
+            hipLaunchKernelGGL((k_tile<T, MODE, true>), dim3(g2), dim3(threads), lds_tile, s,
+                               (T *)state, pd, ws, tau, partial);
         else
-            hipLaunchKernelGGL((k_tile<T, MODE, false>), dim3(g2), dim3(threads), lds, s, (T *)state,
-                               pd, ws, tau, halv, partial);
+            hipLaunchKernelGGL((k_tile<T, MODE, false>), dim3(g2), dim3(threads), lds_tile, s,
+                               (T *)state, pd, ws, tau, partial);
         return hip_check(hipGetLastError(), "k_tile launch");
     }
     hipLaunchKernelGGL((k_pass<T, MODE>), dim3(grid), dim3(kBlock), lds, s, (T *)state, pd, ws,
@@ -697,6 +794,12 @@ extern "C" sd_status sd_bind_workspace(sd_plan_t *p, void *dev_ptr, size_t bytes
             if (st != SD_OK) return st;
         }
     }
+    if (!p->layer_data.empty()) {
+        sd_status st = hip_check(hipMemcpy((uint8_t *)dev_ptr + p->ws_off_layers, p->layer_data.data(),
+                                           p->layer_data.size() * sizeof(uint64_t), hipMemcpyHostToDevice),
+                                 "layer table upload");
+        if (st != SD_OK) return st;
+    }
     p->ws = dev_ptr;
     p->ws_bytes = bytes;
     p->bound = true;
@@ -716,6 +819,14 @@ extern "C" sd_status sd_evolve(const sd_plan_t *p, void *state, sd_dtype dtype, 
     const int K = (int)p->groups.size();
     if (K == 0 || steps == 0) return SD_OK;
     auto seq = step_schedule(K, order);
+    if (p->mode != SD_MODE_TILES) {
+        for (int64_t st = 0; st < steps; ++st)
+            for (auto &gf : seq) {
+                sd_status r = run_group_reference(p, state, dtype, gf.first, dt * gf.second, s);
+                if (r != SD_OK) return r;
+            }
+        return SD_OK;
+    }
     for (int64_t st = 0; st < steps; ++st)
         for (auto &gf : seq) {
             const double tau = dt * gf.second;
@@ -839,15 +950,56 @@ extern "C" sd_status sd_sync(void *stream) {
 // ---------------------------------------------------------------------------
 // ensemble
 // ---------------------------------------------------------------------------
+// Instances are independent; within an instance the passes of a step are
+// sequential.  Level l of a step holds pass l of the step's pass sequence of
+// every instance that has one; a level is one k_tile_multi launch over all
+// its instances' tiles (grouped by tile size), so a step costs as many
+// launches as the longest instance sequence, whatever the number of
+// instances.  One step's launches are captured once as a HIP graph on an
+// internal stream and replayed.
 struct sd_ensemble {
     std::vector<const sd_plan_t *> plans;
     sd_dtype dtype = SD_C64;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t ws_needed = 0;
+    int max_levels = 0;
+    // graph cache
+    hipStream_t cstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double g_dt = 0;
+    int g_order = 0;
+    std::vector<void *> g_states;
+    std::vector<int> g_small;   // instances run through sd_evolve each step
+    ~sd_ensemble() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (cstream) (void)hipStreamDestroy(cstream);
+    }
 };
+
+namespace {
+// pass indices of one step of an instance, with the fraction of dt of each
+std::vector<std::pair<int, double>> step_passes(const sd_plan_t *p, sd_dtype dt, int order) {
+    std::vector<std::pair<int, double>> out;
+    const Program &P = p->prog[dt];
+    const int K = (int)p->groups.size();
+    for (auto &gf : step_schedule(K, order))
+        for (int i = P.group_first[gf.first]; i < P.group_first[gf.first + 1]; ++i)
+            out.push_back({i, gf.second});
+    return out;
+}
+}  // namespace
 
 extern "C" sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t count, sd_dtype dtype,
                                         sd_ensemble **out) {
     if (!plans || !out || count <= 0) return fail(SD_ERR_ARG, "sd_ensemble_create: bad argument");
     if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_ensemble_create: bad dtype");
+    *out = nullptr;
     sd_ensemble *e = new sd_ensemble();
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) {
@@ -855,34 +1007,180 @@ extern "C" sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t c
             return fail(SD_ERR_ARG, "sd_ensemble_create: null plan");
         }
         e->plans.push_back(plans[i]);
+        e->max_levels = std::max<int>(e->max_levels, (int)step_passes(plans[i], dtype, 2).size());
     }
     e->dtype = dtype;
+    e->ws_needed = ((int64_t)e->max_levels * count * (int64_t)sizeof(MultiSeg) + 255) / 256 * 256;
     *out = e;
     return SD_OK;
 }
 
 extern "C" sd_status sd_ensemble_workspace_bytes(const sd_ensemble *e, int64_t *bytes) {
     if (!e || !bytes) return fail(SD_ERR_ARG, "sd_ensemble_workspace_bytes: null argument");
-    *bytes = 256;
+    *bytes = std::max<int64_t>(e->ws_needed, 256);
     return SD_OK;
 }
 
 extern "C" sd_status sd_ensemble_bind_workspace(sd_ensemble *e, void *dev_ptr, size_t bytes,
                                                 void *stream) {
     (void)stream;
-    if (!e || !dev_ptr || bytes < 256) return fail(SD_ERR_WORKSPACE, "sd_ensemble_bind_workspace");
+    if (!e || !dev_ptr) return fail(SD_ERR_ARG, "sd_ensemble_bind_workspace: null argument");
+    if ((int64_t)bytes < e->ws_needed) return fail(SD_ERR_WORKSPACE, "ensemble workspace too small");
+    if (((uintptr_t)dev_ptr) & 255) return fail(SD_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    e->ws = dev_ptr;
+    e->ws_bytes = bytes;
+    if (e->exec) {
+        (void)hipGraphExecDestroy(e->exec);
+        e->exec = nullptr;
+    }
     return SD_OK;
 }
+
+namespace {
+struct LevelLaunch {
+    int64_t off, nseg, total;
+    int D;
+};
+
+// Build and upload the level tables of one step; instances with any tile
+// below the multi-instance kernel's minimum are listed in *small instead.
+sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order,
+                       std::vector<LevelLaunch> *launches, std::vector<int> *small) {
+    const int n_inst = (int)e->plans.size();
+    std::vector<std::vector<std::pair<int, double>>> seq(n_inst);
+    std::vector<char> is_small(n_inst, 0);
+    int levels = 0;
+    small->clear();
+    for (int i = 0; i < n_inst; ++i) {
+        seq[i] = step_passes(e->plans[i], e->dtype, order);
+        for (auto &pf : seq[i])
+            if (e->plans[i]->prog[e->dtype].passes[pf.first].D < kTileMinD) is_small[i] = 1;
+        if (is_small[i]) {
+            small->push_back(i);
+            continue;
+        }
+        levels = std::max<int>(levels, (int)seq[i].size());
+    }
+    std::vector<MultiSeg> host;
+    launches->clear();
+    for (int l = 0; l < levels; ++l) {
+        for (int D = kTileMinD; D <= kMaxTileLog2; ++D) {
+            LevelLaunch L{(int64_t)host.size(), 0, 0, D};
+            for (int i = 0; i < n_inst; ++i) {
+                if (is_small[i] || l >= (int)seq[i].size()) continue;
+                const sd_plan_t *p = e->plans[i];
+                const PassHost &ph = p->prog[e->dtype].passes[seq[i][l].first];
+                if (ph.D != D) continue;
+                MultiSeg sg;
+                sg.state = states[i];
+                sg.ws = (const uint8_t *)p->ws;
+                sg.pd = (const PassDev *)((const uint8_t *)p->ws + p->ws_off_prog[e->dtype] +
+                                          (int64_t)seq[i][l].first * sizeof(PassDev));
+                sg.tau = dt * seq[i][l].second;
+                sg.first_item = L.total;
+                sg.n_tiles = (int64_t)1 << (p->n - ph.D);
+                L.total += sg.n_tiles;
+                host.push_back(sg);
+                ++L.nseg;
+            }
+            if (L.nseg) launches->push_back(L);
+        }
+    }
+    if ((int64_t)(host.size() * sizeof(MultiSeg)) > (int64_t)e->ws_bytes)
+        return fail(SD_ERR_WORKSPACE, "ensemble workspace too small for the segment tables");
+    if (host.empty()) return SD_OK;
+    return hip_check(hipMemcpy(e->ws, host.data(), host.size() * sizeof(MultiSeg), hipMemcpyHostToDevice),
+                     "ensemble segment upload");
+}
+
+template <typename T>
+sd_status launch_levels(sd_ensemble *e, const std::vector<LevelLaunch> &launches, hipStream_t s) {
+    std::call_once(g_once, init_device_props);
+    const MultiSeg *dsegs = (const MultiSeg *)e->ws;
+    for (auto &L : launches) {
+        const int threads = 1 << (L.D - kLE);
+        const int per_cu = L.D >= 13 ? 1 : 2;
+        const int grid = (int)std::min<int64_t>(L.total, (int64_t)std::max(1, g_num_cu) * per_cu);
+        const size_t lds = ((size_t)16 << L.D) + (size_t)4 * 4 * threads;
+        hipLaunchKernelGGL((k_tile_multi<T, true>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
+                           (int)L.nseg, L.total);
+        sd_status r = hip_check(hipGetLastError(), "k_tile_multi launch");
+        if (r != SD_OK) return r;
+    }
+    return SD_OK;
+}
+}  // namespace
 
 extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, double dt, int64_t steps,
                                         int32_t order, void *stream) {
     if (!e || !states) return fail(SD_ERR_ARG, "sd_ensemble_evolve: null argument");
-    for (int64_t st = 0; st < steps; ++st)
-        for (size_t i = 0; i < e->plans.size(); ++i) {
-            sd_status r = sd_evolve(e->plans[i], states[i], e->dtype, dt, 1, order, stream);
+    if (order != 1 && order != 2) return fail(SD_ERR_ARG, "sd_ensemble_evolve: order must be 1 or 2");
+    if (steps < 0 || !std::isfinite(dt)) return fail(SD_ERR_ARG, "sd_ensemble_evolve: bad steps/dt");
+    if (!e->ws) return fail(SD_ERR_WORKSPACE, "sd_ensemble_evolve: no workspace bound");
+    for (size_t i = 0; i < e->plans.size(); ++i) {
+        if (!states[i]) return fail(SD_ERR_ARG, "sd_ensemble_evolve: null state");
+        if (!e->plans[i]->bound) return fail(SD_ERR_WORKSPACE, "sd_ensemble_evolve: plan without workspace");
+    }
+    if (steps == 0) return SD_OK;
+    hipStream_t user = (hipStream_t)stream;
+    sd_status r;
+    if (!e->cstream) {
+        r = hip_check(hipStreamCreateWithFlags(&e->cstream, hipStreamNonBlocking), "ensemble stream");
+        if (r != SD_OK) return r;
+        r = hip_check(hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming), "ensemble event");
+        if (r != SD_OK) return r;
+        r = hip_check(hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming), "ensemble event");
+        if (r != SD_OK) return r;
+    }
+    std::vector<void *> st(states, states + e->plans.size());
+    if (!(e->exec && e->g_dt == dt && e->g_order == order && e->g_states == st)) {
+        if (e->exec) {
+            (void)hipGraphExecDestroy(e->exec);
+            e->exec = nullptr;
+        }
+        if (e->graph) {
+            (void)hipGraphDestroy(e->graph);
+            e->graph = nullptr;
+        }
+        // no earlier replay may still read the segment tables being replaced
+        r = hip_check(hipStreamSynchronize(e->cstream), "ensemble stream sync");
+        if (r != SD_OK) return r;
+        std::vector<LevelLaunch> launches;
+        r = build_levels(e, states, dt, order, &launches, &e->g_small);
+        if (r != SD_OK) return r;
+        r = hip_check(hipStreamBeginCapture(e->cstream, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (r != SD_OK) return r;
+        r = e->dtype == SD_C64 ? launch_levels<float2>(e, launches, e->cstream)
+                               : launch_levels<double2>(e, launches, e->cstream);
+        hipGraph_t g = nullptr;
+        sd_status r2 = hip_check(hipStreamEndCapture(e->cstream, &g), "end capture");
+        if (r != SD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (r2 != SD_OK) return r2;
+        e->graph = g;
+        r = hip_check(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0), "graph instantiate");
+        if (r != SD_OK) return r;
+        e->g_dt = dt;
+        e->g_order = order;
+        e->g_states = st;
+    }
+    r = hip_check(hipEventRecord(e->ev_in, user), "event record");
+    if (r != SD_OK) return r;
+    r = hip_check(hipStreamWaitEvent(e->cstream, e->ev_in, 0), "stream wait");
+    if (r != SD_OK) return r;
+    for (int64_t k = 0; k < steps; ++k) {
+        r = hip_check(hipGraphLaunch(e->exec, e->cstream), "graph launch");
+        if (r != SD_OK) return r;
+        for (int i : e->g_small) {
+            r = sd_evolve(e->plans[i], states[i], e->dtype, dt, 1, order, e->cstream);
             if (r != SD_OK) return r;
         }
-    return SD_OK;
+    }
+    r = hip_check(hipEventRecord(e->ev_out, e->cstream), "event record");
+    if (r != SD_OK) return r;
+    return hip_check(hipStreamWaitEvent(user, e->ev_out, 0), "stream wait");
 }
 
 extern "C" void sd_ensemble_destroy(sd_ensemble *e) { delete e; }

@@ -5,7 +5,7 @@
 namespace sd {
 
 constexpr int kMaxD = 16;            // tile dims a record can describe
-constexpr int kMaxPassTerms = 1024;  // Lambda terms per pass (LDS budget)
+constexpr int kMaxPassTerms = 256;   // Lambda terms per pass (LDS budget)
 
 struct alignas(256) PassDev {
     int32_t n;          // qubits

@@ -14,6 +14,7 @@ extern "C" void sd_plan_options_default(sd_plan_options *o) {
     o->tile_log2_c128 = 13;
     o->coalesce_log2_c64 = 4;
     o->coalesce_log2_c128 = 3;
+    o->mode = SD_MODE_TILES;
 }
 
 namespace {
@@ -62,6 +63,8 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
         opt.coalesce_log2_c64 >= opt.tile_log2_c64 ||
         opt.coalesce_log2_c128 >= opt.tile_log2_c128)
         return fail(SD_ERR_RANGE, "sd_plan: tile/coalescing options out of range");
+    if (opt.mode != SD_MODE_TILES && opt.mode != SD_MODE_PAPER_LAYERS && opt.mode != SD_MODE_TERMWISE)
+        return fail(SD_ERR_ARG, "sd_plan: unknown mode");
     auto t0 = std::chrono::steady_clock::now();
     sd_plan_t *p = new sd_plan_s();
     p->n = h->n;
@@ -93,6 +96,8 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
         p->gate_flat.push_back(std::move(flat));
     }
     p->paper_model_passes = model;
+    p->mode = opt.mode;
+    build_layers(*p);
 
     sd_status st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c64,
                                    opt.coalesce_log2_c64, &p->prog[SD_C64]);
@@ -103,12 +108,15 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
         delete p;
         return st;
     }
-    // workspace: packed pass tables for both dtypes + reduction scratch
+    // workspace: packed pass tables for both dtypes, the layer-mode diagonal
+    // tables, then the reduction scratch
     int64_t off = 0;
     for (int d = 0; d < 2; ++d) {
         p->ws_off_prog[d] = off;
         off += (pack_size(p->prog[d]) + 255) / 256 * 256;
     }
+    p->ws_off_layers = off;
+    off += (int64_t)(p->layer_data.size() * sizeof(uint64_t) + 255) / 256 * 256;
     p->ws_off_scratch = off;
     off += 64 * 1024;  // FP64 partial sums
     p->ws_needed = off;

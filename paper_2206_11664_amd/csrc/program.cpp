@@ -48,34 +48,35 @@ struct Coords {
 
 // Register-round schedule for the on-chip transform of a tile with D
 // coordinates (span coordinates 0..rho-1, spectators rho..D-1).  A thread
-// holds 32 amplitudes: the 5 tile coordinates of the current round vary over
-// them, the remaining D-5 coordinates are the thread index (lowest first, so
-// consecutive lanes touch consecutive on-chip slots).  Span coordinates are
-// taken five at a time; a short last chunk is filled with the highest other
-// coordinates, which are carried without butterflies.  Lambda is applied in
-// the round of the last chunk, between the two transforms.
+// holds 2^kRegBits amplitudes: the kRegBits tile coordinates of the current
+// round vary over them, the remaining coordinates are the thread index (lowest
+// first, so consecutive lanes touch consecutive on-chip slots).  Span
+// coordinates are taken kRegBits at a time; a short last chunk is filled with
+// the highest other coordinates, which are carried without butterflies.
+// Lambda is applied in the round of the last chunk, between the two transforms.
 sd_status plan_rounds(PassHost *ps) {
     PassHost &p = *ps;
     const int D = p.D, rho = p.rho;
     p.nr = 0;
-    if (D < 5) {  // tiny tile: handled by the generic kernel only
+    const int RB = kRegBits;
+    if (D < 2 * RB) {  // tiny tile: handled by the generic kernel only
         p.lam_round = 0;
     } else {
         auto fill = [&](int r, std::vector<int> bits, uint32_t bm) {
-            for (int b = D - 1; (int)bits.size() < 5 && b >= 0; --b)
+            for (int b = D - 1; (int)bits.size() < RB && b >= 0; --b)
                 if (std::find(bits.begin(), bits.end(), b) == bits.end()) bits.push_back(b);
-            for (int i = 0; i < 5; ++i) p.reg[r][i] = (uint8_t)bits[i];
+            for (int i = 0; i < RB; ++i) p.reg[r][i] = (uint8_t)bits[i];
             p.bmask[r] = bm;
         };
         if (rho == 0) {
             fill(0, {}, 0u);
             p.lam_round = 0;
         } else {
-            p.nr = (rho + 4) / 5;
+            p.nr = (rho + RB - 1) / RB;
             if (p.nr > 4) return fail(SD_ERR_INTERNAL, "too many register rounds");
             for (int r = 0; r < p.nr; ++r) {
                 std::vector<int> bits;
-                for (int b = 5 * r; b < std::min(rho, 5 * r + 5); ++b) bits.push_back(b);
+                for (int b = RB * r; b < std::min(rho, RB * r + RB); ++b) bits.push_back(b);
                 fill(r, bits, (1u << bits.size()) - 1);
             }
             p.lam_round = p.nr - 1;
@@ -85,8 +86,8 @@ sd_status plan_rounds(PassHost *ps) {
     const int L = p.lam_round;
     auto pattern = [&](uint32_t z) {
         uint32_t w = 0;
-        if (D >= 5)
-            for (int i = 0; i < 5; ++i) w |= ((z >> p.reg[L][i]) & 1u) << i;
+        if (D >= 2 * RB)
+            for (int i = 0; i < RB; ++i) w |= ((z >> p.reg[L][i]) & 1u) << i;
         return w;
     };
     const size_t m = p.zeta.size();
@@ -146,8 +147,12 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
     p.D = (int)p.basis.size();
     if (p.D > 31) return fail(SD_ERR_INTERNAL, "tile dimension above 31");
 
-    // pivots: low bits 0..c-1 first (unit vectors), then the rest
+    // pivots: low bits 0..c-1 first (unit vectors), then for every further
+    // vector its highest remaining bit.  High pivots leave the low address bits
+    // to the tile index, so tiles with consecutive indices (processed at the
+    // same time by neighbouring blocks) touch neighbouring cache lines.
     Echelon piv;
+    piv.high_pivot = true;
     for (int q = 0; q < c; ++q) piv.insert(1ull << q);
     for (uint64_t b : p.basis) piv.insert(b);
     if (piv.dim() != p.D) return fail(SD_ERR_INTERNAL, "tile basis rank mismatch");
@@ -268,25 +273,44 @@ sd_status compile_program(int n, const std::vector<Term> &T,
     const int cc = std::min(c, n);
     const int Dcap = std::min(D_max, n);
     for (size_t g = 0; g < groups.size(); ++g) {
-        // split into sub-groups whose tile space (X span + low bits) fits
-        std::vector<Echelon> spaces;
+        // Split into sub-groups whose tile space (X span + low bits) fits.
+        // Sub-groups are grown one at a time: first every remaining term whose
+        // X part already lies in the span joins (no growth), then the term
+        // whose addition lets the most remaining terms in for free is added.
         std::vector<std::vector<int64_t>> subs;
-        for (int64_t k : groups[g]) {
-            const uint64_t x = T[k].x;
-            int pick = -1;
-            for (size_t s = 0; s < subs.size() && pick < 0; ++s)
-                if ((int)subs[s].size() < kMaxPassTerms && spaces[s].contains(x)) pick = (int)s;
-            for (size_t s = 0; s < subs.size() && pick < 0; ++s)
-                if ((int)subs[s].size() < kMaxPassTerms && spaces[s].dim() < Dcap) pick = (int)s;
-            if (pick < 0) {
-                Echelon e;
-                for (int q = 0; q < cc; ++q) e.insert(1ull << q);
-                spaces.push_back(e);
-                subs.emplace_back();
-                pick = (int)subs.size() - 1;
+        std::vector<int64_t> rest(groups[g].begin(), groups[g].end());
+        while (!rest.empty()) {
+            Echelon span;
+            for (int q = 0; q < cc; ++q) span.insert(1ull << q);
+            std::vector<int64_t> cur;
+            while (true) {
+                std::vector<int64_t> keep;
+                for (int64_t k : rest) {
+                    if ((int)cur.size() < kMaxPassTerms && span.contains(T[k].x))
+                        cur.push_back(k);
+                    else
+                        keep.push_back(k);
+                }
+                rest.swap(keep);
+                if (rest.empty() || span.dim() >= Dcap || (int)cur.size() >= kMaxPassTerms) break;
+                size_t best = 0;
+                int best_score = -1;
+                for (size_t a = 0; a < rest.size(); ++a) {
+                    Echelon t2 = span;
+                    t2.insert(T[rest[a]].x);
+                    int score = 0;
+                    for (int64_t k : rest)
+                        if (t2.contains(T[k].x)) ++score;
+                    if (score > best_score) {
+                        best_score = score;
+                        best = a;
+                    }
+                }
+                span.insert(T[rest[best]].x);
+                cur.push_back(rest[best]);
+                rest.erase(rest.begin() + (long)best);
             }
-            spaces[pick].insert(x);
-            subs[pick].push_back(k);
+            subs.push_back(std::move(cur));
         }
         for (auto &s : subs) {
             PassHost ps;

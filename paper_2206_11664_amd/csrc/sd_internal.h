@@ -28,6 +28,7 @@ struct Echelon {
     std::vector<uint64_t> vec, comb;
     std::vector<int> piv;
     int inserted = 0;
+    bool high_pivot = false;  // pivot = highest (else lowest) set bit of the remainder
     // Reduce v against the basis; returns the remainder, and the combination
     // of basis vectors used in *used (as generator combination).
     uint64_t reduce(uint64_t v, uint64_t *used = nullptr) const;
@@ -107,6 +108,7 @@ SynthResult synthesize(int n, const std::vector<Row> &terms, const SynthOptions 
 // ---------------------------------------------------------------------------
 constexpr int kMaxTileLog2 = 13;   // on-chip tile limit (LDS, FP64 staging)
 constexpr int kMinTileLog2 = 6;
+constexpr int kRegBits = 4;        // tile coordinates per register round
 
 struct PassHost {
     int32_t group = -1;
@@ -124,11 +126,26 @@ struct PassHost {
     double coef_abs_sum = 0;        // sum |c_k| (bounds the phase angle)
     // register-round schedule of the on-chip Walsh-Hadamard (see device.hip)
     int nr = 0;                     // chunks of <= 5 span coordinates
-    uint8_t reg[4][5] = {};         // tile coordinates held in registers per chunk
+    uint8_t reg[4][8] = {};         // tile coordinates held in registers per chunk
     uint32_t bmask[4] = {};         // which of the 5 register slots are butterflied
     int lam_round = 0;              // chunk whose round applies Lambda
     std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
                                     // pattern on the registers of lam_round
+};
+
+// One HBM pass of the layer-by-layer (paper) execution of a group
+// application, in application order.
+struct LayerOp {
+    enum Kind { H = 0, CNOT_FAN = 1, DIAG = 2 } kind;
+    int a = -1;             // H: qubit; CNOT_FAN: control
+    uint64_t mask = 0;      // CNOT_FAN: target mask
+    // DIAG: multiply by i^{s_sign * popcount(x & smask)} (-1)^{sum_pairs x_a popcount(x & m)}
+    //       exp(-i tau_frac * dt * sum_k c_k (-1)^{popcount(x & z_k)}) * scale
+    int s_sign = 0;
+    uint64_t smask = 0;
+    int64_t cz_off = 0, cz_n = 0;      // pairs (a, mask) as 2 words each in layer_data
+    int64_t lam_off = 0, lam_n = 0;    // (zmask, coef bits) as 2 words each
+    double scale = 1.0;
 };
 
 struct Program {
@@ -162,4 +179,16 @@ struct sd_plan_s {
     int64_t ws_off_prog[2] = {0, 0};   // byte offsets of packed pass tables
     int64_t ws_off_scratch = 0;        // reduction scratch
     bool bound = false;
+    // layer-by-layer and term-by-term execution
+    int32_t mode = SD_MODE_TILES;
+    std::vector<std::vector<sd::LayerOp>> layers;   // per group, one application
+    std::vector<uint64_t> layer_data;               // packed CZ pairs and Lambda terms
+    int64_t ws_off_layers = 0;
 };
+
+namespace sd {
+void build_layers(sd_plan_s &p);
+// one application of group g in the plan's layer or term-by-term mode (layers.hip)
+sd_status run_group_reference(const sd_plan_s *p, void *state, sd_dtype dtype, int g, double tau,
+                              struct ihipStream_t *stream);
+}

@@ -39,7 +39,7 @@ bool Echelon::insert(uint64_t v) {
     int idx = inserted++;
     if (r == 0) return false;
     cm ^= (idx < 64) ? (1ull << idx) : 0ull;
-    int p = ctz(r);
+    int p = high_pivot ? 63 - __builtin_clzll(r) : ctz(r);
     for (size_t i = 0; i < vec.size(); ++i)
         if ((vec[i] >> p) & 1) {
             vec[i] ^= r;

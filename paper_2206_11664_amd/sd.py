@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsdiag.so")
 SD_OK, SD_ERR_ARG, SD_ERR_PARSE, SD_ERR_RANGE, SD_ERR_WORKSPACE, SD_ERR_HIP, \
     SD_ERR_INTERNAL, SD_ERR_STATE = range(8)
 SD_C64, SD_C128 = 0, 1
+SD_MODE_TILES, SD_MODE_PAPER_LAYERS, SD_MODE_TERMWISE = 0, 1, 2
 GATE_NAMES = {0: "H", 1: "S", 2: "CNOT", 3: "CZ"}
 
 # every symbol include/sd.h declares
@@ -43,7 +44,7 @@ class SdError(RuntimeError):
 class sd_plan_options(ctypes.Structure):
     _fields_ = [("skip_rule", ctypes.c_int32), ("tile_log2_c64", ctypes.c_int32),
                 ("tile_log2_c128", ctypes.c_int32), ("coalesce_log2_c64", ctypes.c_int32),
-                ("coalesce_log2_c128", ctypes.c_int32)]
+                ("coalesce_log2_c128", ctypes.c_int32), ("mode", ctypes.c_int32)]
 
 
 class sd_plan_info(ctypes.Structure):
@@ -306,6 +307,7 @@ def sd_inner(a, b, n_qubits: int, stream=None) -> complex:
 
 
 def sd_ensemble_create(plans: Sequence[int], dtype: int) -> int:
+    """plans: raw plan handles (``Plan.p``), each with a bound workspace."""
     arr = (vp * len(plans))(*plans)
     out = vp()
     _check(lib().sd_ensemble_create(arr, len(plans), dtype, ctypes.byref(out)))

@@ -221,3 +221,37 @@ def test_full_size_n28_widest_group_vs_oracle():
         err = l2(got, want)
         print(f"[gpu] n28 group dtype={dtype} L2={err:.3e}", flush=True)
         assert err <= (1e-10 if dtype == sd.SD_C128 else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_ensemble_of_uneven_instances(dtype):
+    # uneven sizes; n = 8 runs below the multi-instance kernel's tile minimum
+    models = workloads.xxz_ensemble(count=5, seed=4, nmin=8, nmax=15, steps=20)
+    models[0] = workloads.xxz_ensemble(count=1, seed=9, nmin=8, nmax=8, steps=20)[0]
+    print("[gpu] ensemble sizes", [m.n for m in models], flush=True)
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in models]
+    ens = sd.sd_ensemble_create([p.p for p in plans], dtype)
+    ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+    sd.sd_ensemble_bind_workspace(ens, ws)
+    states = [torch.from_numpy(m.initial_state()).to(TDT[dtype]).cuda() for m in models]
+    singles = [s.clone() for s in states]
+    sd.sd_ensemble_evolve(ens, states, 0.05, 12, 2)
+    sd.sd_ensemble_evolve(ens, states, 0.05, 8, 2)   # graph replay path
+    for p, s in zip(plans, singles):
+        p.evolve(s, 0.05, 20, 2)
+    torch.cuda.synchronize()
+    for m, s, s1 in zip(models, states, singles):
+        got = s.cpu().numpy().astype(np.complex128)
+        assert torch.equal(s, s1), m.n
+        want = oracle.evolve(m.n, m.paulis, m.coeffs, m.initial_state(), 0.05, 20, 2)
+        assert l2(got, want) <= TOL[dtype], (m.n, l2(got, want))
+    sd.sd_ensemble_destroy(ens)
+
+
+@pytest.mark.parametrize("mode", [sd.SD_MODE_PAPER_LAYERS, sd.SD_MODE_TERMWISE])
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_reference_modes(mode, dtype):
+    # the paper's layer-by-layer circuit execution and the term-by-term
+    # baseline give the same state as the oracle (and as the tiles)
+    m = workloads.random_klocal(n=12, m=120, seed=21, init_seed=22)
+    check(m, dtype, 0.05, 3, 2, dict(mode=mode))
