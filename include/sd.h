@@ -187,12 +187,40 @@ typedef struct {
     const uint32_t *zeta;      /* per term: Lambda Z-mask in tile coordinates  */
     const uint64_t *ztile;     /* per term: physical Z part for the tile sign  */
     const double *coef;        /* per term: signed coefficient                */
+    uint32_t z_sign;           /* span coordinates with an extra Z in the CZ/S
+                                  layer: it multiplies tile coordinate y by
+                                  i^{q(y)} (-1)^{popcount(y & z_sign)}, q(y) =
+                                  sum_i y_i popcount(cz_s[i] & y)             */
 } sd_pass_view;
 
 /* Device pass list for one dtype, in application order for group order 1. */
 sd_status sd_plan_pass_count(const sd_plan_t *p, sd_dtype dt, int32_t *count);
 sd_status sd_plan_export_pass(const sd_plan_t *p, sd_dtype dt, int32_t i,
                               sd_pass_view *v);
+
+/* Register-round schedule of one tile pass (the on-chip Walsh-Hadamard of
+   the rho span coordinates runs in rounds of 4 coordinates held in
+   registers; see DESIGN notes of the tile kernel).  Chunk r holds span
+   coordinates in register slots 0..popcount(bmask[r])-1 and other tile
+   coordinates in the remaining slots; iflag/dflag mark slots whose
+   coordinate carries an S / a Z of the CZ/S layer; later[r] is the mask of
+   span coordinates of the chunks after r.  Lambda is applied in the round of
+   lam_round; terms (in the pass view's order) are grouped by their Lambda
+   pattern on that round's register slots: pattern w owns terms
+   bucket[w] .. bucket[w+1]-1.  Views stay valid until sd_plan_destroy.
+   Errors: SD_ERR_ARG, SD_ERR_RANGE (pass index). */
+typedef struct {
+    int32_t n_rounds;          /* chunks (0 when rho = 0: one Lambda round)    */
+    int32_t lam_round;
+    int32_t reg[4][4];
+    uint32_t bmask[4];
+    uint32_t iflag[4];
+    uint32_t dflag[4];
+    uint32_t later[4];
+    const int32_t *bucket;     /* 17 offsets                                    */
+} sd_round_view;
+sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int32_t i,
+                                sd_round_view *v);
 
 void sd_plan_destroy(sd_plan_t *p);
 

@@ -53,14 +53,18 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         for (int j = p.c; j < p.D; ++j) d.u_hi[j - p.c] = p.u[j];
         for (int j = 0; j < p.D; ++j) d.mr[j] = p.mr[j];
         for (int j = 0; j < p.rho; ++j) d.B[j] = p.B[j];
+        d.zq = p.zq;
         int f = 0;
         for (int q = 0; q < n; ++q)
-            if ((p.free_mask >> q) & 1) d.free_pos[f++] = (uint8_t)q;
+            if ((p.free_mask >> q) & 1) d.free_pos[f++] = q;
         d.nr = p.nr;
         d.lam_round = p.lam_round;
         for (int r = 0; r < 4; ++r) {
-            for (int b = 0; b < 8; ++b) d.reg[r][b] = p.reg[r][b];
+            for (int b = 0; b < 4; ++b) d.reg[r][b] = p.reg[r][b];
             d.bmask[r] = p.bmask[r];
+            d.iflag[r] = p.iflag[r];
+            d.dflag[r] = p.dflag[r];
+            d.later[r] = p.later[r];
         }
         for (int w = 0; w < 33; ++w) d.bucket[w] = p.bucket.empty() ? 0 : p.bucket[w];
         d.coef_abs_sum = p.coef_abs_sum;
@@ -98,8 +102,9 @@ __device__ __forceinline__ double2 mul_ipow(double2 a, int q) {
     }
 }
 
-__device__ __forceinline__ int quad_form(const uint32_t *B, int rho, uint32_t y) {
-    int q = 0;
+// exponent of the CZ/S layer's phase i^{q(y)} (-1)^{popcount(y & zq)}
+__device__ __forceinline__ int quad_form(const uint32_t *B, uint32_t zq, int rho, uint32_t y) {
+    int q = 2 * __popc(zq & y);
     for (int i = 0; i < rho; ++i)
         if ((y >> i) & 1) q += __popc(B[i] & y);
     return q;
@@ -179,7 +184,7 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
         __syncthreads();
         if (rho > 0) {
             for (int64_t t = threadIdx.x; t < size; t += blockDim.x)
-                tile[t] = mul_ipow(tile[t], quad_form(pd.B, rho, (uint32_t)t & rmask));
+                tile[t] = mul_ipow(tile[t], quad_form(pd.B, pd.zq, rho, (uint32_t)t & rmask));
             wht_lds(tile, D, rho);
         }
         if (MODE == 0) {
@@ -195,7 +200,7 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
             if (rho > 0) {
                 wht_lds(tile, D, rho);
                 for (int64_t t = threadIdx.x; t < size; t += blockDim.x)
-                    tile[t] = mul_ipow(tile[t], -quad_form(pd.B, rho, (uint32_t)t & rmask));
+                    tile[t] = mul_ipow(tile[t], -quad_form(pd.B, pd.zq, rho, (uint32_t)t & rmask));
             }
             __syncthreads();
             for (int64_t p = threadIdx.x; p < size; p += blockDim.x) {
@@ -236,12 +241,38 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
 // LDS.  The LDS slot of tile coordinate t is t ^ fold(t >> 3) (fold = XOR of
 // its 3-bit groups): whenever the three lowest thread-index bits address three
 // adjacent coordinates, the 8 lanes of a 128-byte LDS phase hit distinct banks.
-// Rounds run in a loop over a runtime chunk index so that each routine exists
-// once in the code object.
+// The slot map is linear over GF(2), so every address is a per-thread base
+// XOR a uniform offset; the tile sits at LDS address 0 and addresses are
+// plain byte offsets (no static LDS in these kernels).
+//
+// The CZ/S layer costs no per-amplitude work.  The planner puts its quadratic
+// form in a basis where no chunk has a CZ inside it, so the layer factors
+// into: an S on a chunk coordinate, applied as an i twiddle inside that
+// coordinate's butterfly; a Z on a chunk coordinate and the CZs between a
+// chunk coordinate and a coordinate of a later chunk (a thread-index bit in
+// this round), which are sign patterns (-1)^{l.j} on the register index j
+// before the butterflies, i.e. an XOR l on their output index.  That XOR is
+// folded into the address the round writes to, and into the address the
+// mirrored inverse round reads from (a Walsh-Hadamard transform of the
+// permuted data applies the inverse sign pattern by itself).  In the Lambda
+// round, the XOR is folded into the signs of Lambda's terms instead.
 constexpr int kLE = 4;
 constexpr int kE = 1 << kLE;
 constexpr int kTileMinD = 10;
 constexpr int kMaxThreads = 1 << (kMaxTileLog2 - kLE);
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) dvec2 lds_c2;
+__device__ __forceinline__ double2 lds_ld(uint32_t a) {
+    const dvec2 v = *(const lds_c2 *)(size_t)a;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void lds_st(uint32_t a, double2 v) {
+    dvec2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(lds_c2 *)(size_t)a = w;
+}
 
 __device__ __forceinline__ uint32_t lds_slot(uint32_t t) {
     uint32_t h = t >> 3;
@@ -249,21 +280,35 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t t) {
     return t ^ (h & 7u);
 }
 
-// e^{i theta} in FP64: Taylor polynomials of cos and sin at theta / 2^halv
-// (|theta / 2^halv| <= 1/4, truncation < 1e-17), then halv double-angle steps.
+// dynamic LDS of k_tile: tile, per-thread round addresses, term arrays, uniforms
+__host__ __device__ constexpr size_t tile_lds_bytes(int D, int threads) {
+    return ((size_t)16 << D) + (size_t)8 * 4 * threads + (size_t)28 * kMaxPassTerms + 64 + 64;
+}
+
+// e^{i theta}: Taylor polynomials of cos and sin at x = theta / 2^halv
+// (|x| <= 1/4), then halv double-angle steps.  FULL: degrees 12/13 (truncation
+// below 1e-17, for complex128 states); otherwise degrees 8/9 (below 3e-13,
+// far under the complex64 rounding of the result).
+template <bool FULL>
 __device__ __forceinline__ void cis(double th, int halv, double &c, double &s) {
     const double x = ldexp(th, -halv);
     const double x2 = x * x;
-    double pc = 1.0 / 479001600.0;
-    pc = fma(pc, x2, -1.0 / 3628800.0);
-    pc = fma(pc, x2, 1.0 / 40320.0);
+    double pc, ps;
+    if (FULL) {
+        pc = 1.0 / 479001600.0;
+        pc = fma(pc, x2, -1.0 / 3628800.0);
+        pc = fma(pc, x2, 1.0 / 40320.0);
+        ps = 1.0 / 6227020800.0;
+        ps = fma(ps, x2, -1.0 / 39916800.0);
+        ps = fma(ps, x2, 1.0 / 362880.0);
+    } else {
+        pc = 1.0 / 40320.0;
+        ps = 1.0 / 362880.0;
+    }
     pc = fma(pc, x2, -1.0 / 720.0);
     pc = fma(pc, x2, 1.0 / 24.0);
     pc = fma(pc, x2, -0.5);
     c = fma(pc, x2, 1.0);
-    double ps = 1.0 / 6227020800.0;
-    ps = fma(ps, x2, -1.0 / 39916800.0);
-    ps = fma(ps, x2, 1.0 / 362880.0);
     ps = fma(ps, x2, -1.0 / 5040.0);
     ps = fma(ps, x2, 1.0 / 120.0);
     ps = fma(ps, x2, -1.0 / 6.0);
@@ -275,100 +320,156 @@ __device__ __forceinline__ void cis(double th, int halv, double &c, double &s) {
     }
 }
 
-// (re, im) * i^e, e in 0..3
-__device__ __forceinline__ void rot_ipow(double &re, double &im, uint32_t e) {
-    const double a = re, b = im;
-    re = (e & 1u) ? -b : a;
-    im = (e & 1u) ? a : b;
-    if (e & 2u) {
-        re = -re;
-        im = -im;
-    }
-}
-
-__device__ __forceinline__ void bfly(double (&re)[kE], double (&im)[kE], uint32_t bm) {
+// butterflies on register bit L.  Forward: (a, c) -> (a + w c, a - w c) with
+// w = 1 or i (the S of that coordinate applied first).  Backward, the inverse
+// up to the factor 2: (A, C) -> (A + C, conj(w) (A - C)).
+template <int L, bool TW>
+__device__ __forceinline__ void bfly_fwd(double (&re)[kE], double (&im)[kE]) {
 #pragma unroll
-    for (int b = 0; b < kLE; ++b) {
-        if (!((bm >> b) & 1u)) continue;
-#pragma unroll
-        for (int j = 0; j < kE; ++j)
-            if (!((j >> b) & 1)) {
-                const int k = j | (1 << b);
-                const double ar = re[j], ai = im[j], cr = re[k], ci = im[k];
+    for (int j = 0; j < kE; ++j)
+        if (!((j >> L) & 1)) {
+            const int k = j | (1 << L);
+            const double ar = re[j], ai = im[j], cr = re[k], ci = im[k];
+            if (TW) {
+                re[j] = ar - ci;
+                im[j] = ai + cr;
+                re[k] = ar + ci;
+                im[k] = ai - cr;
+            } else {
                 re[j] = ar + cr;
                 im[j] = ai + ci;
                 re[k] = ar - cr;
                 im[k] = ai - ci;
             }
+        }
+}
+
+template <int L, bool TW>
+__device__ __forceinline__ void bfly_bwd(double (&re)[kE], double (&im)[kE]) {
+#pragma unroll
+    for (int j = 0; j < kE; ++j)
+        if (!((j >> L) & 1)) {
+            const int k = j | (1 << L);
+            const double ar = re[j], ai = im[j], cr = re[k], ci = im[k];
+            re[j] = ar + cr;
+            im[j] = ai + ci;
+            if (TW) {
+                re[k] = ai - ci;
+                im[k] = cr - ar;
+            } else {
+                re[k] = ar - cr;
+                im[k] = ai - ci;
+            }
+        }
+}
+
+template <int L, bool FWD>
+__device__ __forceinline__ void stage(double (&re)[kE], double (&im)[kE], uint32_t tw) {
+    if ((tw >> L) & 1u) {
+        if (FWD) bfly_fwd<L, true>(re, im);
+        else bfly_bwd<L, true>(re, im);
+    } else {
+        if (FWD) bfly_fwd<L, false>(re, im);
+        else bfly_bwd<L, false>(re, im);
     }
 }
 
+// butterflies on register bits 0..nb-1; every case rewrites all registers
+template <bool FWD>
+__device__ __forceinline__ void stages(double (&re)[kE], double (&im)[kE], int nb, uint32_t tw) {
+    switch (nb) {
+        case 4:
+            stage<0, FWD>(re, im, tw);
+            stage<1, FWD>(re, im, tw);
+            stage<2, FWD>(re, im, tw);
+            stage<3, FWD>(re, im, tw);
+            break;
+        case 3:
+            stage<0, FWD>(re, im, tw);
+            stage<1, FWD>(re, im, tw);
+            stage<2, FWD>(re, im, tw);
+            break;
+        case 2:
+            stage<0, FWD>(re, im, tw);
+            stage<1, FWD>(re, im, tw);
+            break;
+        case 1:
+            stage<0, FWD>(re, im, tw);
+            break;
+        default:
+            break;
+    }
+}
+
+__device__ __forceinline__ double2 to_c128(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ double2 to_c128(double2 v) { return v; }
+__device__ __forceinline__ void from_c128(float2 &o, double2 v) { o = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void from_c128(double2 &o, double2 v) { o = v; }
+
 // One tile pass over tiles t0, t0 + stride, ... < t1 of the pass `pdp` (the
-// whole pass when called with blockIdx.x, n_tiles, gridDim.x).  MODE 1 adds
-// this block's share of <psi|H_pass|psi> to acc.
-template <typename T, int MODE, bool PREFETCH>
+// whole pass when called with blockIdx.x, n_tiles, gridDim.x).  MODE 0
+// evolves in place, MODE 1 adds this block's share of <psi|H_pass|psi> to
+// acc.  OFF is the type of in-state byte offsets: uint32_t when the state is
+// at most 4 GiB (32-bit offsets from a per-tile scalar base), else uint64_t.
+template <typename T, int MODE, typename OFF>
 __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *__restrict__ pdp,
                                           const uint8_t *__restrict__ ws, double tau, int64_t t0,
                                           int64_t t1, int64_t stride, double &acc) {
-    // dynamic LDS: the tile (16 B per amplitude), then the per-thread round bases
-    extern __shared__ double2 lds[];
-    uint32_t *thr_base = (uint32_t *)(lds + ((size_t)1 << pdp->D));
-    // the pass's term arrays live in LDS for the whole launch: reading them from
-    // global memory inside the tile loop would make every such read wait for
-    // all outstanding state loads and stores (one counter covers both)
-    __shared__ double cks[kMaxPassTerms];
-    __shared__ double coef[kMaxPassTerms];
-    __shared__ uint64_t ztile[kMaxPassTerms];
-    __shared__ uint32_t zeta[kMaxPassTerms];
-    // per-round uniform data, staged so that no byte-sized pass field is read
-    // from global memory inside the tile loop (such reads are vector loads)
-    __shared__ uint32_t s_rs[4][kLE];
-    __shared__ uint32_t s_free[64];
-    __syncthreads();  // a previous call of this block may still read the arrays
+    constexpr bool FULL = sizeof(T) == 16;
+    extern __shared__ double2 lds_dyn[];
     const PassDev &pd = *pdp;
+    const int D = pd.D, TL = D - kLE, c = pd.c, m = pd.m, nr = pd.nr;
+    const uint32_t T_ = blockDim.x;
+    const uint32_t tid = threadIdx.x;
+    char *lbase = (char *)lds_dyn;
+    uint2 *thr = (uint2 *)(lbase + ((size_t)16 << D));
+    double *cks = (double *)(lbase + ((size_t)16 << D) + (size_t)32 * T_);
+    double *coef = cks + kMaxPassTerms;
+    uint64_t *ztile = (uint64_t *)(coef + kMaxPassTerms);
+    uint32_t *zeta = (uint32_t *)(ztile + kMaxPassTerms);
+    uint32_t *s_rs = zeta + kMaxPassTerms;  // [4][kLE] byte offsets of register coordinates
+    __syncthreads();  // a previous call of this block may still read the arrays
     int halv = 0;
     if (MODE == 0) {
         const double th = fabs(tau) * pd.coef_abs_sum;
         while (halv < 60 && ldexp(th, -halv) > 0.25) ++halv;
     }
-    const int D = pd.D, TL = D - kLE, c = pd.c, m = pd.m, nr = pd.nr, rho = pd.rho;
-    const uint32_t tid = threadIdx.x;
-    const int n_free = pd.n_free;
-    if (tid < 4 * kLE) s_rs[tid / kLE][tid % kLE] = lds_slot(1u << pd.reg[tid / kLE][tid % kLE]);
-    if (tid < 64) s_free[tid] = pd.free_pos[tid];
+    if (tid < 4 * kLE) s_rs[tid] = lds_slot(1u << pd.reg[tid / kLE][tid % kLE]) * 16u;
     {
         const uint8_t *tb = ws + pd.term_off;
         const int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
-        for (int k = tid; k < m; k += blockDim.x) {
+        for (int k = tid; k < m; k += T_) {
             zeta[k] = ((const uint32_t *)tb)[k];
             ztile[k] = ((const uint64_t *)(tb + o2))[k];
             coef[k] = ((const double *)(tb + o2 + 8 * (int64_t)m))[k];
         }
     }
-    const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
     const double scale = pd.scale;
     const int nrounds = nr > 0 ? nr : 1;
 
     // ---- per-thread constants (tile independent) ----
     // scatter/gather: element j of thread t is pivot pattern t + (j << TL)
-    uint64_t off_t = 0;
+    OFF off_t = 0;
     uint32_t tc_t = 0;
     for (int i = 0; i < TL; ++i)
         if ((tid >> i) & 1) {
-            off_t ^= i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c];
+            off_t ^= (OFF)(i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]) * (OFF)sizeof(T);
             tc_t ^= pd.mr[i];
         }
-    const uint32_t sl_t = lds_slot(tc_t);
+    const uint32_t sl_t = lds_slot(tc_t) * 16u;
     // uniform increments of the Gray-code address walks over the kE elements
-    uint64_t pv[kLE];
+    OFF pv[kLE];
     uint32_t sv[kLE];
 #pragma unroll
     for (int b = 0; b < kLE; ++b) {
         const int i = TL + b;
-        pv[b] = i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c];
-        sv[b] = lds_slot(pd.mr[i]);
+        pv[b] = (OFF)(i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]) * (OFF)sizeof(T);
+        sv[b] = lds_slot(pd.mr[i]) * 16u;
     }
-    // rounds: thread-index bits fill the tile coordinates outside reg[r], lowest first
+    // rounds: thread-index bits fill the tile coordinates outside reg[r],
+    // lowest first.  thr[r] = (address the forward round reads, address it
+    // writes); the second carries the thread's output XOR.
+    uint32_t sgnb = 0;  // tile coordinates for the signs of Lambda's terms
     for (int r = 0; r < nrounds; ++r) {
         uint32_t regm = 0;
         for (int b = 0; b < kLE; ++b) regm |= 1u << pd.reg[r][b];
@@ -379,84 +480,87 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                 bt |= ((tid >> i) & 1u) << q;
                 ++i;
             }
-        thr_base[r * blockDim.x + tid] = bt;
-    }
-    // CZ/S phase exponents i^{q(y)} of this thread's amplitudes in chunk 0
-    uint32_t qe = 0;
-    if (nr > 0) {
-        const uint32_t b0 = thr_base[tid];
-        for (int j = 0; j < kE; ++j) {
-            uint32_t t = b0;
-            for (int b = 0; b < kLE; ++b)
-                if ((j >> b) & 1) t ^= 1u << pd.reg[0][b];
-            const uint32_t y = t & rmask;
-            uint32_t q = 0;
-            for (int i2 = 0; i2 < rho; ++i2)
-                if ((y >> i2) & 1) q += __popc(pd.B[i2] & y);
-            qe |= (q & 3u) << (2 * j);
+        uint32_t pm = 0;
+        for (int l = 0; l < kLE; ++l)
+            if ((pd.bmask[r] >> l) & 1u) {
+                const int a = pd.reg[r][l];
+                const uint32_t bit = (__popc(pd.B[a] & pd.later[r] & bt) ^ (pd.dflag[r] >> l)) & 1u;
+                pm |= bit << a;
+            }
+        const uint32_t rd = lds_slot(bt) * 16u;
+        if (r == nrounds - 1) {
+            sgnb = bt ^ pm;
+            thr[r * T_ + tid] = make_uint2(rd, rd);
+        } else {
+            thr[r * T_ + tid] = make_uint2(rd, lds_slot(bt ^ pm) * 16u);
         }
     }
 
+    // Element address = tile base XOR in-tile offset (the pivot vectors may
+    // have bits at free positions, so the two are not added).  Offsets are in
+    // bytes from the state pointer.
     T pre[kE];
-    auto tile_base = [&](int64_t ti) {
+    const char *sbase = (const char *)state;
+    auto tile_off = [&](int64_t ti) {
         uint64_t xT = 0;
-        for (int i = 0; i < n_free; ++i)
-            if ((ti >> i) & 1) xT |= (uint64_t)1 << s_free[i];
-        return xT;
+        for (int i = 0; i < pd.n_free; ++i)
+            if ((ti >> i) & 1) xT |= (uint64_t)1 << pd.free_pos[i];
+        return (OFF)xT * (OFF)sizeof(T);
     };
-    auto load_tile = [&](uint64_t xT) {
-        uint64_t co = xT ^ off_t;
+    auto load_tile = [&](OFF xb) {
+        OFF co = xb ^ off_t;
         asm volatile("" : "+v"(co));
 #pragma unroll
         for (int j = 0; j < kE; ++j) {
             if (j) co ^= pv[__builtin_ctz(j)];
-            pre[j] = state[co];
+            pre[j] = *(const T *)(sbase + co);
         }
     };
-    __syncthreads();
-
     auto scatter = [&]() {
         uint32_t cs = sl_t;
         asm volatile("" : "+v"(cs));
 #pragma unroll
         for (int j = 0; j < kE; ++j) {
             if (j) cs ^= sv[__builtin_ctz(j)];
-            lds[cs] = make_double2((double)pre[j].x, (double)pre[j].y);
+            lds_st(cs, to_c128(pre[j]));
         }
     };
-    auto signs = [&](uint64_t xT) {
-        for (int k = tid; k < m; k += blockDim.x) {
+    auto signs = [&](OFF xb) {
+        const uint64_t xT = (uint64_t)xb / sizeof(T);
+        for (int k = tid; k < m; k += T_) {
             const double v = coef[k];
             cks[k] = (__popcll(ztile[k] & xT) & 1) ? -v : v;
         }
     };
+    __syncthreads();
+
     auto transform = [&]() {
         double re[kE], im[kE];
         const int total = nr > 0 ? 2 * nr - 1 : 1;
         for (int step = 0; step < total; ++step) {
             const int r = step < nrounds ? step : 2 * nr - 2 - step;
-            const bool lam_round = step == nrounds - 1;
-            const uint32_t base = thr_base[r * blockDim.x + tid];
+            const bool lam = step == nrounds - 1;
+            const bool fwd = step < nrounds - 1;
+            const uint2 ab = thr[r * T_ + tid];
+            const uint32_t ra = fwd || lam ? ab.x : ab.y;
+            const uint32_t wa = fwd ? ab.y : ab.x;
             uint32_t rs[kLE];
 #pragma unroll
-            for (int b = 0; b < kLE; ++b) rs[b] = s_rs[r][b];
+            for (int b = 0; b < kLE; ++b) rs[b] = s_rs[r * kLE + b];
             {
-                uint32_t cs = lds_slot(base);
+                uint32_t cs = ra;
 #pragma unroll
                 for (int jj = 0; jj < kE; ++jj) {
                     if (jj) cs ^= rs[__builtin_ctz(jj)];
-                    const double2 a = lds[cs];
+                    const double2 a = lds_ld(cs);
                     re[jj ^ (jj >> 1)] = a.x;
                     im[jj ^ (jj >> 1)] = a.y;
                 }
             }
-            if (step == 0 && nr > 0) {
-#pragma unroll
-                for (int j = 0; j < kE; ++j) rot_ipow(re[j], im[j], (qe >> (2 * j)) & 3u);
-            }
-            const uint32_t bm = pd.bmask[r];
-            bfly(re, im, bm);
-            if (lam_round) {
+            const int nb = __popc(pd.bmask[r]);
+            const uint32_t tw = pd.iflag[r];
+            if (lam) {
+                stages<true>(re, im, nb, tw);
                 // phi over the kE register patterns: bucket sums of the signed
                 // coefficients, then a kE-point Walsh-Hadamard of the sums
                 double A[kE];
@@ -466,7 +570,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                     const int k1 = pd.bucket[w + 1];
                     for (int k = pd.bucket[w]; k < k1; ++k) {
                         const double ck = cks[k];
-                        sacc += (__popc(zeta[k] & base) & 1) ? -ck : ck;
+                        sacc += (__popc(zeta[k] & sgnb) & 1) ? -ck : ck;
                     }
                     A[w] = sacc;
                 }
@@ -479,43 +583,42 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                             A[j] = a0 + a1;
                             A[j | (1 << b)] = a0 - a1;
                         }
-                if (MODE == 0) {
-#pragma unroll
-                    for (int j = 0; j < kE; ++j) {
-                        double cc, ss;
-                        cis(-tau * A[j], halv, cc, ss);
-                        cc *= scale;
-                        ss *= scale;
-                        const double ar = re[j], ai = im[j];
-                        re[j] = fma(ar, cc, -ai * ss);
-                        im[j] = fma(ar, ss, ai * cc);
-                    }
-                    bfly(re, im, bm);
-                } else {
+                if (MODE == 1) {
 #pragma unroll
                     for (int j = 0; j < kE; ++j) acc += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
+                    break;
                 }
-            }
-            if (MODE == 1 && lam_round) break;
-            if (step == total - 1 && nr > 0) {
 #pragma unroll
-                for (int j = 0; j < kE; ++j) rot_ipow(re[j], im[j], (4u - ((qe >> (2 * j)) & 3u)) & 3u);
+                for (int j = 0; j < kE; ++j) {
+                    double cc, ss;
+                    cis<FULL>(-tau * A[j], halv, cc, ss);
+                    cc *= scale;
+                    ss *= scale;
+                    const double ar = re[j], ai = im[j];
+                    re[j] = fma(ar, cc, -ai * ss);
+                    im[j] = fma(ar, ss, ai * cc);
+                }
+                stages<false>(re, im, nb, tw);
+            } else if (fwd) {
+                stages<true>(re, im, nb, tw);
+            } else {
+                stages<false>(re, im, nb, tw);
             }
             {
-                uint32_t cs = lds_slot(base);
+                uint32_t cs = wa;
                 asm volatile("" : "+v"(cs));
 #pragma unroll
                 for (int jj = 0; jj < kE; ++jj) {
                     if (jj) cs ^= rs[__builtin_ctz(jj)];
-                    lds[cs] = make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]);
+                    lds_st(cs, make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]));
                 }
             }
             __syncthreads();
         }
     };
-    auto gather = [&](uint64_t xT) {
+    auto gather = [&](OFF xb) {
         uint32_t cs = sl_t;
-        uint64_t co = xT ^ off_t;
+        OFF co = xb ^ off_t;
         asm volatile("" : "+v"(cs), "+v"(co));
 #pragma unroll
         for (int j = 0; j < kE; ++j) {
@@ -523,62 +626,64 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                 cs ^= sv[__builtin_ctz(j)];
                 co ^= pv[__builtin_ctz(j)];
             }
-            st_amp(state, (int64_t)co, lds[cs]);
+            from_c128(*(T *)((char *)state + co), lds_ld(cs));
         }
     };
 
     int64_t ti = t0;
-    if (PREFETCH) {
+    // complex128 tiles skip the register prefetch: it would not fit the
+    // register budget of two waves per SIMD
+    if (MODE == 0 && sizeof(T) == 8) {
         // Software pipeline.  The loop is rotated so that on every path into
         // the loop only the next tile's loads are outstanding; inside the body
         // the stores of the current tile are issued after them, so the wait
         // for the next tile's data before its scatter does not wait for the
         // stores (one counter tracks both, in issue order).
         if (ti < t1) {
-            uint64_t xT_cur = tile_base(ti);
-            load_tile(xT_cur);
+            OFF tp_cur = tile_off(ti);
+            load_tile(tp_cur);
             scatter();
-            signs(xT_cur);
+            signs(tp_cur);
             int64_t tn = ti + stride;
-            uint64_t xT_next = 0;
+            OFF tp_next = tp_cur;
             if (tn < t1) {
-                xT_next = tile_base(tn);
-                load_tile(xT_next);
+                tp_next = tile_off(tn);
+                load_tile(tp_next);
             }
             __syncthreads();
             while (true) {
                 transform();
-                if (MODE == 0) gather(xT_cur);
+                gather(tp_cur);
                 __syncthreads();
                 if (tn >= t1) break;
-                xT_cur = xT_next;
+                tp_cur = tp_next;
                 scatter();
-                signs(xT_cur);
+                signs(tp_cur);
                 tn += stride;
                 if (tn < t1) {
-                    xT_next = tile_base(tn);
-                    load_tile(xT_next);
+                    tp_next = tile_off(tn);
+                    load_tile(tp_next);
                 }
                 __syncthreads();
             }
         }
     } else {
         for (; ti < t1; ti += stride) {
-            const uint64_t xT_cur = tile_base(ti);
-            load_tile(xT_cur);
+            const OFF tp = tile_off(ti);
+            load_tile(tp);
             scatter();
-            signs(xT_cur);
+            signs(tp);
             __syncthreads();
             transform();
-            if (MODE == 0) gather(xT_cur);
+            if (MODE == 0) gather(tp);
             __syncthreads();
         }
     }
 }
 
 // block sum in a fixed order: wave sums, then one value per wave through LDS
-__device__ __forceinline__ double block_sum_waves(double acc) {
-    __shared__ double red[kMaxThreads / 64];
+// (the slots after the tile-pass arrays)
+__device__ __forceinline__ double block_sum_waves(double acc, double *red) {
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -588,14 +693,16 @@ __device__ __forceinline__ double block_sum_waves(double acc) {
     return s2;
 }
 
-template <typename T, int MODE, bool PREFETCH>
+template <typename T, int MODE, typename OFF>
 __global__ void __launch_bounds__(kMaxThreads)
 k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
        double tau, double *__restrict__ partial) {
     double acc = 0.0;
-    tile_pass<T, MODE, PREFETCH>(state, pdp, ws, tau, blockIdx.x, pdp->n_tiles, gridDim.x, acc);
+    tile_pass<T, MODE, OFF>(state, pdp, ws, tau, blockIdx.x, pdp->n_tiles, gridDim.x, acc);
     if (MODE == 1) {
-        const double s2 = block_sum_waves(acc);
+        extern __shared__ double2 lds_dyn[];
+        double *red = (double *)((char *)lds_dyn + tile_lds_bytes(pdp->D, blockDim.x) - 64);
+        const double s2 = block_sum_waves(acc, red);
         if (threadIdx.x == 0) partial[blockIdx.x] += s2;
     }
 }
@@ -612,7 +719,7 @@ struct MultiSeg {
     int64_t n_tiles;
 };
 
-template <typename T, bool PREFETCH>
+template <typename T>
 __global__ void __launch_bounds__(kMaxThreads)
 k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
     const int64_t lo = (total * (int64_t)blockIdx.x) / gridDim.x;
@@ -623,7 +730,7 @@ k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
         const int64_t a = sg.first_item, b = sg.first_item + sg.n_tiles;
         const int64_t s0 = a > lo ? a : lo, s1 = b < hi ? b : hi;
         if (s0 >= s1) continue;
-        tile_pass<T, 0, PREFETCH>((T *)sg.state, sg.pd, sg.ws, sg.tau, s0 - a, s1 - a, 1, acc);
+        tile_pass<T, 0, uint32_t>((T *)sg.state, sg.pd, sg.ws, sg.tau, s0 - a, s1 - a, 1, acc);
     }
 }
 
@@ -688,32 +795,52 @@ static sd_status hip_check(hipError_t e, const char *what) {
 }
 
 static int g_num_cu = 0;
-static bool g_prefetch = true;   // SD_PREFETCH=0 disables the software pipeline
 static bool g_generic = false;   // SD_GENERIC_KERNEL=1 routes every pass to k_pass
 static std::once_flag g_once;
+static sd_status g_init_status = SD_OK;
+
+template <typename K>
+static void set_lds(K kernel, int bytes) {
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// The tile kernels address LDS by absolute byte offsets with the tile at 0:
+// they must not have static LDS (it would be placed before the dynamic part).
+template <typename K>
+static bool no_static_lds(K kernel) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void *)kernel) != hipSuccess) return false;
+    return a.sharedSizeBytes == 0;
+}
 
 static void init_device_props() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) g_num_cu = prop.multiProcessorCount;
-    if (const char *e = std::getenv("SD_PREFETCH")) g_prefetch = std::atoi(e) != 0;
     if (const char *e = std::getenv("SD_GENERIC_KERNEL")) g_generic = std::atoi(e) != 0;
-    const int lds = (1 << kMaxTileLog2) * 16 + 4 * 4 * kMaxThreads;
-    (void)hipFuncSetAttribute((const void *)k_pass<float2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_pass<float2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_pass<double2, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_pass<double2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<float2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<float2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<double2, 0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<double2, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<float2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<double2, 0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<float2, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile<double2, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile_multi<float2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_tile_multi<double2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const int lds_generic = (1 << kMaxTileLog2) * 16;
+    set_lds(k_pass<float2, 0>, lds_generic);
+    set_lds(k_pass<float2, 1>, lds_generic);
+    set_lds(k_pass<double2, 0>, lds_generic);
+    set_lds(k_pass<double2, 1>, lds_generic);
+    const int lds = (int)tile_lds_bytes(kMaxTileLog2, kMaxThreads);
+    set_lds(k_tile<float2, 0, uint32_t>, lds);
+    set_lds(k_tile<float2, 1, uint32_t>, lds);
+    set_lds(k_tile<double2, 0, uint32_t>, lds);
+    set_lds(k_tile<double2, 1, uint32_t>, lds);
+    set_lds(k_tile<float2, 0, uint64_t>, lds);
+    set_lds(k_tile<float2, 1, uint64_t>, lds);
+    set_lds(k_tile<double2, 0, uint64_t>, lds);
+    set_lds(k_tile<double2, 1, uint64_t>, lds);
+    set_lds(k_tile_multi<float2>, lds);
+    set_lds(k_tile_multi<double2>, lds);
+    const bool ok = no_static_lds(k_tile<float2, 0, uint32_t>) && no_static_lds(k_tile<float2, 1, uint32_t>) &&
+                    no_static_lds(k_tile<double2, 0, uint32_t>) && no_static_lds(k_tile<double2, 1, uint32_t>) &&
+                    no_static_lds(k_tile<float2, 0, uint64_t>) && no_static_lds(k_tile<float2, 1, uint64_t>) &&
+                    no_static_lds(k_tile<double2, 0, uint64_t>) && no_static_lds(k_tile<double2, 1, uint64_t>) &&
+                    no_static_lds(k_tile_multi<float2>) && no_static_lds(k_tile_multi<double2>);
+    if (!ok) g_init_status = fail(SD_ERR_INTERNAL, "tile kernels were built with static LDS");
 }
 
 static int grid_for(int64_t tiles) {
@@ -731,6 +858,7 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
     double *partial = (double *)(ws + p->ws_off_scratch);
     const int64_t tiles = (int64_t)1 << (p->n - ph.D);
     const int grid_evolve = grid_for(tiles);  // also runs the one-time LDS attribute setup
+    if (g_init_status != SD_OK) return fail(g_init_status, "device initialisation failed");
     const int grid = MODE == 1 ? (int)std::min<int64_t>(tiles, kPartialSlots / 2) : grid_evolve;
     if (ph.D > kMaxTileLog2 || (int)ph.terms.size() > kMaxPassTerms)
         return fail(SD_ERR_INTERNAL, "pass exceeds the on-chip tile limits");
@@ -740,16 +868,17 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
         const int threads = 1 << (ph.D - kLE);
         // tiles of 2^13 fill one CU's LDS: one block per CU, next tile
         // prefetched into registers; smaller tiles run two or more blocks per CU
-        const bool pf = g_prefetch;
         const int per_cu = ph.D >= 13 ? 1 : 2;
-        const size_t lds_tile = lds + (size_t)4 * 4 * threads;
+        const size_t lds_tile = tile_lds_bytes(ph.D, threads);
         const int g2 = MODE == 1 ? grid
                                  : (int)std::min<int64_t>(tiles, (int64_t)std::max(1, g_num_cu) * per_cu);
-        if (pf)
-            hipLaunchKernelGGL((k_tile<T, MODE, true>), dim3(g2), dim3(threads), lds_tile, s,
+        // byte offsets inside the state fit 32 bits up to 4 GiB
+        const bool narrow = ((uint64_t)sizeof(T) << p->n) <= ((uint64_t)1 << 32);
+        if (narrow)
+            hipLaunchKernelGGL((k_tile<T, MODE, uint32_t>), dim3(g2), dim3(threads), lds_tile, s,
                                (T *)state, pd, ws, tau, partial);
         else
-            hipLaunchKernelGGL((k_tile<T, MODE, false>), dim3(g2), dim3(threads), lds_tile, s,
+            hipLaunchKernelGGL((k_tile<T, MODE, uint64_t>), dim3(g2), dim3(threads), lds_tile, s,
                                (T *)state, pd, ws, tau, partial);
         return hip_check(hipGetLastError(), "k_tile launch");
     }
@@ -1055,6 +1184,9 @@ sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order
         seq[i] = step_passes(e->plans[i], e->dtype, order);
         for (auto &pf : seq[i])
             if (e->plans[i]->prog[e->dtype].passes[pf.first].D < kTileMinD) is_small[i] = 1;
+        // the multi-instance kernel uses 32-bit in-state offsets
+        const size_t amp = e->dtype == SD_C64 ? sizeof(float2) : sizeof(double2);
+        if (((uint64_t)amp << e->plans[i]->n) > ((uint64_t)1 << 32)) is_small[i] = 1;
         if (is_small[i]) {
             small->push_back(i);
             continue;
@@ -1096,13 +1228,14 @@ sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order
 template <typename T>
 sd_status launch_levels(sd_ensemble *e, const std::vector<LevelLaunch> &launches, hipStream_t s) {
     std::call_once(g_once, init_device_props);
+    if (g_init_status != SD_OK) return fail(g_init_status, "device initialisation failed");
     const MultiSeg *dsegs = (const MultiSeg *)e->ws;
     for (auto &L : launches) {
         const int threads = 1 << (L.D - kLE);
         const int per_cu = L.D >= 13 ? 1 : 2;
         const int grid = (int)std::min<int64_t>(L.total, (int64_t)std::max(1, g_num_cu) * per_cu);
-        const size_t lds = ((size_t)16 << L.D) + (size_t)4 * 4 * threads;
-        hipLaunchKernelGGL((k_tile_multi<T, true>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
+        const size_t lds = tile_lds_bytes(L.D, threads);
+        hipLaunchKernelGGL((k_tile_multi<T>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
                            (int)L.nseg, L.total);
         sd_status r = hip_check(hipGetLastError(), "k_tile_multi launch");
         if (r != SD_OK) return r;

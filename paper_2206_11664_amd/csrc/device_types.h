@@ -20,12 +20,17 @@ struct alignas(256) PassDev {
     uint64_t u_hi[kMaxD];   // physical vectors of tile pivots c..D-1
     uint32_t mr[kMaxD];     // tile coordinates of each pivot vector
     uint32_t B[kMaxD];      // CZ/S quadratic form rows (rho used)
-    uint8_t free_pos[64];   // physical bit of each tile-index bit
-    // register-round schedule (k_tile)
-    int32_t nr;             // Walsh-Hadamard chunks of <= 5 span coordinates
+    uint32_t zq;            // span coordinates with an extra Z in the CZ/S layer
+    int32_t free_pos[64];   // physical bit of each tile-index bit (32-bit words:
+                            // uniform reads of them stay scalar loads)
+    // register-round schedule (k_tile), one entry per chunk
+    int32_t nr;             // chunks of span coordinates (0 when rho = 0)
     int32_t lam_round;      // chunk whose round applies Lambda
-    uint8_t reg[4][8];      // tile coordinates in registers per chunk (5 used)
-    uint32_t bmask[4];      // register slots that get butterflies per chunk
+    int32_t reg[4][4];      // tile coordinates in registers per chunk
+    uint32_t bmask[4];      // register slots that get butterflies (low bits)
+    uint32_t iflag[4];      // slots whose coordinate carries an S (i twiddle)
+    uint32_t dflag[4];      // slots whose coordinate carries a Z
+    uint32_t later[4];      // span coordinates of the chunks after this one
     int32_t bucket[33];     // term offsets by Lambda pattern on reg[lam_round]
     double coef_abs_sum;    // sum |coef| of the pass
 };

@@ -189,6 +189,27 @@ extern "C" sd_status sd_plan_export_pass(const sd_plan_t *p, sd_dtype dt, int32_
     v->zeta = P[i].zeta.data();
     v->ztile = P[i].ztile.data();
     v->coef = P[i].coef.data();
+    v->z_sign = P[i].zq;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int32_t i,
+                                           sd_round_view *v) {
+    if (!p || !v) return fail(SD_ERR_ARG, "sd_plan_export_rounds: null argument");
+    if (dt != SD_C64 && dt != SD_C128) return fail(SD_ERR_ARG, "bad dtype");
+    const auto &P = p->prog[dt].passes;
+    if (i < 0 || i >= (int32_t)P.size()) return fail(SD_ERR_RANGE, "pass index out of range");
+    const PassHost &h = P[i];
+    v->n_rounds = h.nr;
+    v->lam_round = h.lam_round;
+    for (int r = 0; r < 4; ++r) {
+        for (int b = 0; b < 4; ++b) v->reg[r][b] = h.reg[r][b];
+        v->bmask[r] = h.bmask[r];
+        v->iflag[r] = h.iflag[r];
+        v->dflag[r] = h.dflag[r];
+        v->later[r] = h.later[r];
+    }
+    v->bucket = h.bucket.data();
     return SD_OK;
 }
 

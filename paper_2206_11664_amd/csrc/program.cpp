@@ -46,18 +46,177 @@ struct Coords {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Canonical form of the CZ/S layer.
+//
+// The layer multiplies tile coordinate y (span part) by i^{q(y)} with
+// q(y) = sum_i y_i popcount(B_i & y) mod 4: S on the diagonal, CZ off it.
+// q is a Z4-valued quadratic form, q(x ^ y) = q(x) + q(y) + 2 beta(x, y) with
+// the GF(2) bilinear form beta(x, y) = x^T B y.  A change of the span basis
+// (new coordinates y' with y = M y') is free at run time: it only relabels
+// on-chip slots, like the CNOT network.  In the new basis
+//     q(M y') = sum_a d_a y'_a + 2 sum_{a<b} beta(f_a, f_b) y'_a y'_b   (mod 4)
+// with f_a the columns of M and d_a = q(f_a) in Z4.  Symplectic Gram-Schmidt
+// over GF(2) makes beta diagonal when some vector has beta(v, v) = 1, and
+// otherwise a sum of hyperbolic pairs; the chunk layout then keeps the two
+// vectors of every pair in different register chunks.  The kernel needs no
+// per-amplitude phase multiply then: an S (d_a odd) becomes a butterfly with
+// an i twiddle, a Z (d_a >= 2) and every cross-chunk CZ become a relabelling
+// of the butterfly outputs (see the register-round kernel).
+namespace {
+
+int bil(const std::vector<uint32_t> &B, uint32_t x, uint32_t y) {
+    int t = 0;
+    for (uint32_t v = x; v; v &= v - 1) t ^= popc(B[ctz(v)] & y) & 1;
+    return t;
+}
+
+int qform(const std::vector<uint32_t> &B, uint32_t x) {
+    int q = 0;
+    for (uint32_t v = x; v; v &= v - 1) q += popc(B[ctz(v)] & x);
+    return q & 3;
+}
+
+// new span basis f (old coordinates, in final order) and chunk sizes
+void canonical_basis(const std::vector<uint32_t> &B, int rho, std::vector<uint32_t> *f,
+                     std::vector<int> *chunks) {
+    std::vector<uint32_t> W, dg, rad;
+    std::vector<std::pair<uint32_t, uint32_t>> pairs;
+    for (int i = 0; i < rho; ++i) W.push_back(1u << i);
+    while (!W.empty()) {
+        size_t odd = W.size();
+        for (size_t i = 0; i < W.size(); ++i)
+            if (bil(B, W[i], W[i])) {
+                odd = i;
+                break;
+            }
+        if (odd < W.size()) {
+            const uint32_t e = W[odd];
+            W.erase(W.begin() + (long)odd);
+            for (uint32_t &w : W)
+                if (bil(B, w, e)) w ^= e;
+            dg.push_back(e);
+            continue;
+        }
+        size_t pi = W.size(), pj = W.size();
+        for (size_t i = 0; i < W.size() && pi == W.size(); ++i)
+            for (size_t j = i + 1; j < W.size(); ++j)
+                if (bil(B, W[i], W[j])) {
+                    pi = i;
+                    pj = j;
+                    break;
+                }
+        if (pi == W.size()) {
+            rad = W;
+            break;
+        }
+        const uint32_t v = W[pi], x = W[pj];
+        W.erase(W.begin() + (long)pj);
+        W.erase(W.begin() + (long)pi);
+        for (uint32_t &w : W) {
+            const int bx = bil(B, w, x), bv = bil(B, w, v);
+            if (bx) w ^= v;
+            if (bv) w ^= x;
+        }
+        pairs.push_back({v, x});
+    }
+    f->clear();
+    chunks->clear();
+    if (!dg.empty() || pairs.empty()) {
+        // diagonal: with an odd vector e every pair (v, x) turns into the odd,
+        // mutually orthogonal e+v+x, e+v, e+x
+        for (auto &pr : pairs) {
+            const uint32_t e = dg.back();
+            dg.back() = e ^ pr.first ^ pr.second;
+            dg.push_back(e ^ pr.first);
+            dg.push_back(e ^ pr.second);
+        }
+        *f = dg;
+        f->insert(f->end(), rad.begin(), rad.end());
+        for (int left = rho; left > 0; left -= kRegBits) chunks->push_back(std::min(left, kRegBits));
+        return;
+    }
+    // alternating: first vectors of the pairs, the radical, second vectors
+    const int p = (int)pairs.size();
+    for (auto &pr : pairs) f->push_back(pr.first);
+    f->insert(f->end(), rad.begin(), rad.end());
+    for (auto &pr : pairs) f->push_back(pr.second);
+    if (rho >= 2 * kRegBits) {
+        // a pair sits rho - p >= kRegBits positions apart: never in one chunk
+        for (int left = rho; left > 0; left -= kRegBits) chunks->push_back(std::min(left, kRegBits));
+    } else {
+        const int s0 = std::min(kRegBits, rho - p);
+        chunks->push_back(s0);
+        chunks->push_back(rho - s0);
+    }
+}
+
+}  // namespace
+
+// Re-express the pass in the canonical span basis: slots, Lambda masks, the
+// CZ/S form and the exported basis all change together.
+sd_status canonicalize(PassHost *ps) {
+    PassHost &p = *ps;
+    const int rho = p.rho;
+    p.zq = 0;
+    p.chunk.clear();
+    if (rho == 0) return SD_OK;
+    std::vector<uint32_t> f;
+    canonical_basis(p.B, rho, &f, &p.chunk);
+    if ((int)f.size() != rho) return fail(SD_ERR_INTERNAL, "canonical basis size");
+    std::vector<uint64_t> f64(f.begin(), f.end());
+    Coords cf(f64);
+    const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
+    auto to_new = [&](uint32_t y, uint32_t *out) -> bool {
+        uint32_t yn = 0;
+        if (!cf.solve(y & rmask, &yn)) return false;
+        *out = (y & ~rmask) | yn;
+        return true;
+    };
+    std::vector<uint32_t> Bn(rho, 0u);
+    for (int a = 0; a < rho; ++a) {
+        const int d = qform(p.B, f[a]);
+        if (d & 1) Bn[a] |= 1u << a;
+        if (d & 2) p.zq |= 1u << a;
+        for (int b = 0; b < rho; ++b)
+            if (b != a && bil(p.B, f[a], f[b])) Bn[a] |= 1u << b;
+    }
+    // every chunk must be free of CZ inside it
+    int off = 0;
+    for (int s : p.chunk) {
+        const uint32_t cm = ((1u << s) - 1) << off;
+        for (int a = off; a < off + s; ++a)
+            if (Bn[a] & cm & ~(1u << a)) return fail(SD_ERR_INTERNAL, "CZ inside a register chunk");
+        off += s;
+    }
+    for (uint32_t &z : p.zeta)
+        if (!to_new(z, &z)) return fail(SD_ERR_INTERNAL, "Lambda mask outside the tile");
+    for (uint32_t &m : p.mr)
+        if (!to_new(m, &m)) return fail(SD_ERR_INTERNAL, "pivot coordinates outside the tile");
+    std::vector<uint64_t> nb(p.basis);
+    for (int a = 0; a < rho; ++a) {
+        uint64_t v = 0;
+        for (uint32_t w = f[a]; w; w &= w - 1) v ^= p.basis[ctz(w)];
+        nb[a] = v;
+    }
+    p.basis = nb;
+    p.B = Bn;
+    return SD_OK;
+}
+
 // Register-round schedule for the on-chip transform of a tile with D
 // coordinates (span coordinates 0..rho-1, spectators rho..D-1).  A thread
 // holds 2^kRegBits amplitudes: the kRegBits tile coordinates of the current
 // round vary over them, the remaining coordinates are the thread index (lowest
-// first, so consecutive lanes touch consecutive on-chip slots).  Span
-// coordinates are taken kRegBits at a time; a short last chunk is filled with
-// the highest other coordinates, which are carried without butterflies.
-// Lambda is applied in the round of the last chunk, between the two transforms.
+// first, so consecutive lanes touch consecutive on-chip slots).  Chunk r takes
+// the next chunk[r] span coordinates; a short chunk is filled with the highest
+// other coordinates, which are carried without butterflies.  Lambda is
+// applied in the round of the last chunk, between the two transforms.
 sd_status plan_rounds(PassHost *ps) {
     PassHost &p = *ps;
     const int D = p.D, rho = p.rho;
     p.nr = 0;
+    for (int r = 0; r < 4; ++r) p.bmask[r] = p.iflag[r] = p.dflag[r] = p.later[r] = 0;
     const int RB = kRegBits;
     if (D < 2 * RB) {  // tiny tile: handled by the generic kernel only
         p.lam_round = 0;
@@ -72,12 +231,20 @@ sd_status plan_rounds(PassHost *ps) {
             fill(0, {}, 0u);
             p.lam_round = 0;
         } else {
-            p.nr = (rho + RB - 1) / RB;
+            p.nr = (int)p.chunk.size();
             if (p.nr > 4) return fail(SD_ERR_INTERNAL, "too many register rounds");
+            int off = 0;
             for (int r = 0; r < p.nr; ++r) {
                 std::vector<int> bits;
-                for (int b = RB * r; b < std::min(rho, RB * r + RB); ++b) bits.push_back(b);
+                for (int b = off; b < off + p.chunk[r]; ++b) bits.push_back(b);
                 fill(r, bits, (1u << bits.size()) - 1);
+                for (int l = 0; l < p.chunk[r]; ++l) {
+                    const int a = off + l;
+                    if ((p.B[a] >> a) & 1) p.iflag[r] |= 1u << l;
+                    if ((p.zq >> a) & 1) p.dflag[r] |= 1u << l;
+                }
+                off += p.chunk[r];
+                for (int b = off; b < rho; ++b) p.later[r] |= 1u << b;
             }
             p.lam_round = p.nr - 1;
         }
@@ -245,6 +412,7 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
     const uint32_t rmask = (p.rho >= 32) ? ~0u : ((1u << p.rho) - 1);
     if (hset != rmask) return fail(SD_ERR_INTERNAL, "tile H layer does not cover the X span");
 
+
     // Lambda terms in the order of the group (vterm order is fine: they commute)
     p.zeta.clear();
     p.ztile.clear();
@@ -257,6 +425,8 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
         double s = (sr.sign[i] ? -1.0 : 1.0) * (ephase[i] == 2 ? -1.0 : 1.0);
         p.coef.push_back(T[k].c * s);
     }
+    sd_status st = canonicalize(&p);
+    if (st != SD_OK) return st;
     return plan_rounds(&p);
 }
 

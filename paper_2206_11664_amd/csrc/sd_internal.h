@@ -120,14 +120,20 @@ struct PassHost {
     std::vector<int> upiv;          // their pivots (ascending, first c = 0..c-1)
     std::vector<uint32_t> mr;       // column i = tile coords of u[i] (D-bit)
     std::vector<uint32_t> B;        // rho rows of the CZ/S form (bit j of B[i])
+    uint32_t zq = 0;                // span coordinates with an extra Z: the layer
+                                    // is i^{q(y)} (-1)^{popcount(y & zq)}
     std::vector<uint32_t> zeta;     // per term, D-bit mask of Lambda
     std::vector<uint64_t> ztile;    // per term, physical z for the tile sign
     std::vector<double> coef;       // per term, c_k (-1)^{r_k} i^{e_k}
     double coef_abs_sum = 0;        // sum |c_k| (bounds the phase angle)
     // register-round schedule of the on-chip Walsh-Hadamard (see device.hip)
-    int nr = 0;                     // chunks of <= 5 span coordinates
+    int nr = 0;                     // chunks of <= kRegBits span coordinates
+    std::vector<int> chunk;         // span coordinates per chunk (contiguous)
     uint8_t reg[4][8] = {};         // tile coordinates held in registers per chunk
-    uint32_t bmask[4] = {};         // which of the 5 register slots are butterflied
+    uint32_t bmask[4] = {};         // register slots that get butterflies (low bits)
+    uint32_t iflag[4] = {};         // register slots whose coordinate has an S
+    uint32_t dflag[4] = {};         // register slots whose coordinate has a Z
+    uint32_t later[4] = {};         // span coordinates of the chunks after r
     int lam_round = 0;              // chunk whose round applies Lambda
     std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
                                     // pattern on the registers of lam_round

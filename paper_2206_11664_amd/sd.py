@@ -27,7 +27,8 @@ GATE_NAMES = {0: "H", 1: "S", 2: "CNOT", 3: "CZ"}
 EXPORTED = [
     "sd_hamiltonian_create", "sd_hamiltonian_create_masks", "sd_hamiltonian_terms",
     "sd_hamiltonian_destroy", "sd_plan_options_default", "sd_plan", "sd_plan_info_get",
-    "sd_plan_export_group", "sd_plan_pass_count", "sd_plan_export_pass", "sd_plan_destroy",
+    "sd_plan_export_group", "sd_plan_pass_count", "sd_plan_export_pass", "sd_plan_export_rounds",
+    "sd_plan_destroy",
     "sd_bind_workspace", "sd_evolve", "sd_expectation", "sd_norm2", "sd_inner",
     "sd_ensemble_create", "sd_ensemble_workspace_bytes", "sd_ensemble_bind_workspace",
     "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_status_string",
@@ -73,7 +74,14 @@ class sd_pass_view(ctypes.Structure):
                 ("cz_s", ctypes.POINTER(ctypes.c_uint32)),
                 ("zeta", ctypes.POINTER(ctypes.c_uint32)),
                 ("ztile", ctypes.POINTER(ctypes.c_uint64)),
-                ("coef", ctypes.POINTER(ctypes.c_double))]
+                ("coef", ctypes.POINTER(ctypes.c_double)), ("z_sign", ctypes.c_uint32)]
+
+
+class sd_round_view(ctypes.Structure):
+    _fields_ = [("n_rounds", ctypes.c_int32), ("lam_round", ctypes.c_int32),
+                ("reg", (ctypes.c_int32 * 4) * 4), ("bmask", ctypes.c_uint32 * 4),
+                ("iflag", ctypes.c_uint32 * 4), ("dflag", ctypes.c_uint32 * 4),
+                ("later", ctypes.c_uint32 * 4), ("bucket", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -103,6 +111,7 @@ def lib():
         "sd_plan_export_group": (st, [vp, i32, ctypes.POINTER(sd_group_view)]),
         "sd_plan_pass_count": (st, [vp, ctypes.c_int, ctypes.POINTER(i32)]),
         "sd_plan_export_pass": (st, [vp, ctypes.c_int, i32, ctypes.POINTER(sd_pass_view)]),
+        "sd_plan_export_rounds": (st, [vp, ctypes.c_int, i32, ctypes.POINTER(sd_round_view)]),
         "sd_plan_destroy": (None, [vp]),
         "sd_bind_workspace": (st, [vp, vp, ctypes.c_size_t, vp]),
         "sd_evolve": (st, [vp, vp, ctypes.c_int, ctypes.c_double, i64, i32, vp]),
@@ -265,7 +274,17 @@ def sd_plan_export_pass(p: int, dtype: int, i: int) -> dict:
             "basis": arr(v.basis, D), "coalesce_log2": v.coalesce_log2,
             "free_mask": int(v.free_mask), "pivot_vec": arr(v.pivot_vec, D),
             "pivot_coord": arr(v.pivot_coord, D), "cz_s": arr(v.cz_s, r),
-            "zeta": arr(v.zeta, m), "ztile": arr(v.ztile, m), "coef": arr(v.coef, m)}
+            "zeta": arr(v.zeta, m), "ztile": arr(v.ztile, m), "coef": arr(v.coef, m),
+            "z_sign": int(v.z_sign)}
+
+
+def sd_plan_export_rounds(p: int, dtype: int, i: int) -> dict:
+    v = sd_round_view()
+    _check(lib().sd_plan_export_rounds(p, dtype, i, ctypes.byref(v)))
+    return {"n_rounds": v.n_rounds, "lam_round": v.lam_round,
+            "reg": [[v.reg[r][b] for b in range(4)] for r in range(4)],
+            "bmask": list(v.bmask), "iflag": list(v.iflag), "dflag": list(v.dflag),
+            "later": list(v.later), "bucket": [v.bucket[w] for w in range(17)]}
 
 
 def sd_plan_destroy(p: int):

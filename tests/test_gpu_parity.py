@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import workloads
+from tests import groups
 
 torch = pytest.importorskip("torch")
 from paper_2206_11664_amd import sd  # noqa: E402
@@ -255,3 +256,56 @@ def test_reference_modes(mode, dtype):
     # baseline give the same state as the oracle (and as the tiles)
     m = workloads.random_klocal(n=12, m=120, seed=21, init_seed=22)
     check(m, dtype, 0.05, 3, 2, dict(mode=mode))
+
+
+# one large commuting group per case: X-span rank rho up to 13 (four register
+# rounds), CZ/S forms with S, Z and cross-chunk CZ (alternating: no S, CZ
+# pairs split across chunks), tiles of 2^10 and 2^13
+@pytest.mark.parametrize("seed,rho,alt", [(1, 9, False), (2, 9, True), (4, 6, True), (5, 3, True),
+                                          (8, 13, False), (9, 13, True), (7, 11, True)])
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_large_commuting_group(seed, rho, alt, dtype):
+    rng = np.random.default_rng(seed)
+    n = 15
+    ps, cs = groups.commuting_group(rng, n, rho, 60, alternating=alt)
+    m = workloads.Model(f"group{seed}", n, ps, np.asarray(cs))
+    psi0 = workloads.random_state(n, seed)
+    for tile, coal in ((13, 0), (13, 4), (10, 2)):
+        opts = dict(tile_log2_c64=tile, tile_log2_c128=tile, coalesce_log2_c64=coal,
+                    coalesce_log2_c128=min(coal, 3))
+        check(m, dtype, 0.09, 2, 2, opts=opts, psi0=psi0)
+
+
+@pytest.mark.parametrize("seed,rho,alt", [(2, 9, True), (8, 13, False), (9, 13, True)])
+def test_large_group_expectation(seed, rho, alt):
+    rng = np.random.default_rng(seed)
+    n = 15
+    ps, cs = groups.commuting_group(rng, n, rho, 60, alternating=alt)
+    psi0 = workloads.random_state(n, seed + 100)
+    want = oracle.energy(n, ps, np.asarray(cs), psi0)
+    plan = sd.Plan(n, ps, cs).bind()
+    for dtype, tol in ((sd.SD_C128, 1e-10), (sd.SD_C64, 1e-5)):
+        psi = torch.from_numpy(psi0).to(TDT[dtype]).cuda()
+        e = plan.expectation(psi)
+        assert abs(e - want) <= tol * max(1.0, abs(want)), (dtype, e, want)
+
+
+def test_state_above_4gib_uses_wide_offsets():
+    # complex128 at n = 29 is 8 GiB: in-state byte offsets need 64 bits there,
+    # complex64 at n = 29 (4 GiB) still uses 32-bit offsets; both runs of the
+    # benchmark-like workload must agree to the complex64 bar
+    n = 29
+    m = workloads.random_klocal(n=n, m=600, seed=8, init_seed=1)
+    plan = sd.Plan(n, m.paulis, m.coeffs).bind()
+    print("[gpu] n29 wide offsets", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    b = torch.randn(1 << n, dtype=torch.complex128, device="cuda", generator=g)
+    b /= torch.linalg.vector_norm(b)
+    c = b.to(torch.complex64)
+    plan.evolve(b, 0.01, 1, 2)
+    plan.evolve(c, 0.01, 1, 2)
+    torch.cuda.synchronize()
+    assert abs(sd.sd_norm2(b, n) - 1) < 1e-12
+    diff = float(torch.linalg.vector_norm(c.to(torch.complex128) - b))
+    print(f"[gpu] n29 c64 vs c128 L2={diff:.3e}", flush=True)
+    assert diff < 1e-5

@@ -1,7 +1,8 @@
 """Host-side planner tests through the C ABI (no GPU calls): parsing, grouping
 bit-exact against the oracle, the paper's worked examples, brute-force
-checks that every synthesised Clifford diagonalises its group, and an
-emulation of the compiled tile programs against the oracle."""
+checks that every synthesised Clifford diagonalises its group, and two
+emulations against the oracle: of the compiled tile programs as described,
+and of the register-round kernel algorithm that runs them on the GPU."""
 import json
 import os
 
@@ -11,7 +12,7 @@ import pytest
 import oracle
 import workloads
 from paper_2206_11664_amd import sd
-from tests import dense, tile_emulator
+from tests import dense, groups, round_emulator, tile_emulator
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -312,3 +313,82 @@ def test_tile_program_emulation_matches_oracle(case, dtype):
                                0.11, 3, order)
     want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.11, 3, order)
     assert np.abs(got - want).max() < 1e-12
+
+
+# --- the register-round kernel algorithm (emulated on the CPU) -------------------------
+def _export_all(p, dtype):
+    cnt = sd.sd_plan_pass_count(p, dtype)
+    return ([sd.sd_plan_export_pass(p, dtype, i) for i in range(cnt)],
+            [sd.sd_plan_export_rounds(p, dtype, i) for i in range(cnt)])
+
+
+def _check_round_structure(ps, rv):
+    """Chunks hold consecutive span coordinates and no CZ inside a chunk."""
+    rho, B = ps["rho"], [int(v) for v in ps["cz_s"]]
+    nr = rv["n_rounds"]
+    if rho == 0:
+        assert nr == 0
+        return
+    seen = []
+    for r in range(nr):
+        nb = bin(rv["bmask"][r]).count("1")
+        assert rv["bmask"][r] == (1 << nb) - 1 and 1 <= nb <= 4
+        coords = [rv["reg"][r][l] for l in range(nb)]
+        assert coords == list(range(len(seen), len(seen) + nb))
+        seen += coords
+        cm = sum(1 << a for a in coords)
+        for l, a in enumerate(coords):
+            assert B[a] & cm & ~(1 << a) == 0, "CZ inside a register chunk"
+            assert ((rv["iflag"][r] >> l) & 1) == ((B[a] >> a) & 1)
+            assert ((rv["dflag"][r] >> l) & 1) == ((ps["z_sign"] >> a) & 1)
+        assert rv["later"][r] == sum(1 << b for b in range(len(seen), rho))
+    assert seen == list(range(rho)) and rv["lam_round"] == nr - 1
+    bk = rv["bucket"]
+    assert bk[0] == 0 and bk[16] == len(ps["coef"]) and all(bk[w] <= bk[w + 1] for w in range(16))
+
+
+@pytest.mark.parametrize("seed,rho,alt", [(1, 9, False), (2, 9, True), (3, 8, True), (4, 6, True),
+                                          (5, 3, True), (6, 12, False), (7, 11, True),
+                                          (8, 13, False), (9, 13, True)])
+def test_register_rounds_large_group_matches_oracle(seed, rho, alt):
+    # one commuting group of X-span rank rho (alternating: its CZ/S form has no
+    # S, so the planner has to split CZ pairs across chunks)
+    rng = np.random.default_rng(seed)
+    n = 14
+    ps, cs = groups.commuting_group(rng, n, rho, 40, alternating=alt)
+    h, p = plan_for(n, ps, cs, tile_log2_c64=13, tile_log2_c128=13, coalesce_log2_c64=0,
+                    coalesce_log2_c128=0)
+    info = sd.sd_plan_info_get(p)
+    assert info.n_groups == 1
+    passes, rounds = _export_all(p, sd.SD_C64)
+    assert [q["rho"] for q in passes] == [rho]
+    off_diag = any(int(b) & ~(1 << i) for i, b in enumerate(passes[0]["cz_s"]))
+    assert off_diag == alt
+    for q, r in zip(passes, rounds):
+        _check_round_structure(q, r)
+    psi0 = workloads.random_state(n, 3)
+    got = round_emulator.evolve(psi0, n, passes, rounds, info.n_groups, 0.07, 1, 1)
+    want = oracle.evolve(n, ps, cs, psi0, 0.07, 1, 1)
+    assert np.abs(got - want).max() < 1e-13
+
+
+@pytest.mark.parametrize("case", ["klocal", "xxz", "jw", "wide"])
+@pytest.mark.parametrize("dtype", [sd.SD_C64, sd.SD_C128])
+def test_register_rounds_models_match_oracle(case, dtype):
+    if case == "klocal":
+        m, D = workloads.random_klocal(n=12, m=80, seed=5, init_seed=6), 10
+    elif case == "xxz":
+        m, D = workloads.xxz_chain(n=11, steps=3), 10
+    elif case == "jw":
+        m, D = workloads.jw_fermionic(n=11, total=150), 10
+    else:
+        m, D = workloads.random_klocal(n=15, m=300, seed=11, init_seed=2), 13
+    h, p = plan_for(m.n, m.paulis, m.coeffs, tile_log2_c64=D, tile_log2_c128=D)
+    info = sd.sd_plan_info_get(p)
+    passes, rounds = _export_all(p, dtype)
+    for q, r in zip(passes, rounds):
+        _check_round_structure(q, r)
+    psi0 = workloads.random_state(m.n, 3)
+    got = round_emulator.evolve(psi0, m.n, passes, rounds, info.n_groups, 0.11, 1, 2)
+    want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.11, 1, 2)
+    assert np.abs(got - want).max() < 1e-13

@@ -2,9 +2,9 @@
 
 Reads the pass description exported through the C ABI (sd_plan_export_pass)
 and applies it to a small state vector exactly as described in the header:
-gather the tile, multiply by i^{q(y)}, Walsh-Hadamard over the rho span
+gather the tile, multiply by i^{q(y)} (-1)^{popcount(y & z_sign)}, Walsh-Hadamard over the rho span
 coordinates, multiply by exp(-i tau Lambda) 2^-rho, Walsh-Hadamard, multiply by
-i^{-q(y)}, scatter.  It is test code: it checks the planner's arithmetic
+the conjugate phase, scatter.  It is test code: it checks the planner's arithmetic
 against the oracle before any GPU run; it is not the GPU path.
 """
 import numpy as np
@@ -66,6 +66,8 @@ def apply_pass(psi, n, ps, tau):
     for i in range(rho):
         yi = (t >> i) & 1
         q += yi * np.array([bin(int(B[i]) & (int(tt) & rmask)).count("1") for tt in t])
+    zs = int(ps.get("z_sign", 0)) & rmask
+    q += 2 * np.array([bin(int(tt) & zs).count("1") for tt in t])
     ph = (1j) ** (q % 4)
     a = a * ph[None, :]
     a = _wht(a, rho, size)
