@@ -280,10 +280,29 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t t) {
     return t ^ (h & 7u);
 }
 
-// dynamic LDS of k_tile: tile, per-thread round addresses, term arrays, uniforms
-__host__ __device__ constexpr size_t tile_lds_bytes(int D, int threads) {
-    return ((size_t)16 << D) + (size_t)8 * 4 * threads + (size_t)28 * kMaxPassTerms + 64 + 64;
+// Dynamic LDS of k_tile, in bytes from 0: the tile (16 B per amplitude); per
+// thread and round the pair of round addresses (8 B); per term the record
+// {signed coefficient of the current tile, Lambda mask} (16 B) and the record
+// {coefficient, physical Z mask for the tile sign} (16 B); the register
+// offsets of the rounds (64 B); the 17 bucket bounds (80 B); 8 block-sum
+// slots (64 B).
+struct TileLds {
+    uint32_t thr, trec, tsrc, rs, bk, red, total;
+};
+__host__ __device__ inline TileLds tile_lds(int D, int threads, int nrounds, int m) {
+    TileLds l;
+    l.thr = 16u << D;
+    l.trec = l.thr + 8u * (uint32_t)(nrounds * threads);
+    l.tsrc = l.trec + 16u * (uint32_t)m;
+    l.rs = l.tsrc + 16u * (uint32_t)m;
+    l.bk = l.rs + 64u;
+    l.red = l.bk + 80u;
+    l.total = l.red + 64u;
+    return l;
 }
+// the largest layout any pass can ask for (attribute setup)
+constexpr size_t kTileLdsMax =
+    ((size_t)16 << kMaxTileLog2) + 8 * 4 * (size_t)kMaxThreads + 32 * (size_t)kMaxPassTerms + 64 + 80 + 64;
 
 // e^{i theta}: Taylor polynomials of cos and sin at x = theta / 2^halv
 // (|x| <= 1/4), then halv double-angle steps.  FULL: degrees 12/13 (truncation
@@ -363,44 +382,6 @@ __device__ __forceinline__ void bfly_bwd(double (&re)[kE], double (&im)[kE]) {
         }
 }
 
-template <int L, bool FWD>
-__device__ __forceinline__ void stage(double (&re)[kE], double (&im)[kE], uint32_t tw) {
-    if ((tw >> L) & 1u) {
-        if (FWD) bfly_fwd<L, true>(re, im);
-        else bfly_bwd<L, true>(re, im);
-    } else {
-        if (FWD) bfly_fwd<L, false>(re, im);
-        else bfly_bwd<L, false>(re, im);
-    }
-}
-
-// butterflies on register bits 0..nb-1; every case rewrites all registers
-template <bool FWD>
-__device__ __forceinline__ void stages(double (&re)[kE], double (&im)[kE], int nb, uint32_t tw) {
-    switch (nb) {
-        case 4:
-            stage<0, FWD>(re, im, tw);
-            stage<1, FWD>(re, im, tw);
-            stage<2, FWD>(re, im, tw);
-            stage<3, FWD>(re, im, tw);
-            break;
-        case 3:
-            stage<0, FWD>(re, im, tw);
-            stage<1, FWD>(re, im, tw);
-            stage<2, FWD>(re, im, tw);
-            break;
-        case 2:
-            stage<0, FWD>(re, im, tw);
-            stage<1, FWD>(re, im, tw);
-            break;
-        case 1:
-            stage<0, FWD>(re, im, tw);
-            break;
-        default:
-            break;
-    }
-}
-
 __device__ __forceinline__ double2 to_c128(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ __forceinline__ double2 to_c128(double2 v) { return v; }
 __device__ __forceinline__ void from_c128(float2 &o, double2 v) { o = make_float2((float)v.x, (float)v.y); }
@@ -410,8 +391,11 @@ __device__ __forceinline__ void from_c128(double2 &o, double2 v) { o = v; }
 // whole pass when called with blockIdx.x, n_tiles, gridDim.x).  MODE 0
 // evolves in place, MODE 1 adds this block's share of <psi|H_pass|psi> to
 // acc.  OFF is the type of in-state byte offsets: uint32_t when the state is
-// at most 4 GiB (32-bit offsets from a per-tile scalar base), else uint64_t.
-template <typename T, int MODE, typename OFF>
+// at most 4 GiB, else uint64_t.  GEN admits chunks of fewer than kLE span
+// coordinates in rounds other than Lambda's; without it those rounds are
+// straight-line code (four plain butterfly stages between one LDS read and
+// one LDS write).
+template <typename T, int MODE, typename OFF, bool GEN>
 __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *__restrict__ pdp,
                                           const uint8_t *__restrict__ ws, double tau, int64_t t0,
                                           int64_t t1, int64_t stride, double &acc) {
@@ -422,12 +406,13 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     const uint32_t T_ = blockDim.x;
     const uint32_t tid = threadIdx.x;
     char *lbase = (char *)lds_dyn;
-    uint2 *thr = (uint2 *)(lbase + ((size_t)16 << D));
-    double *cks = (double *)(lbase + ((size_t)16 << D) + (size_t)32 * T_);
-    double *coef = cks + kMaxPassTerms;
-    uint64_t *ztile = (uint64_t *)(coef + kMaxPassTerms);
-    uint32_t *zeta = (uint32_t *)(ztile + kMaxPassTerms);
-    uint32_t *s_rs = zeta + kMaxPassTerms;  // [4][kLE] byte offsets of register coordinates
+    const int nrounds = nr > 0 ? nr : 1;
+    const TileLds L = tile_lds(D, (int)T_, nrounds, m);
+    uint2 *thr = (uint2 *)(lbase + L.thr);
+    double2 *trec = (double2 *)(lbase + L.trec);   // .x signed coefficient, .y bits: Lambda mask
+    double2 *tsrc = (double2 *)(lbase + L.tsrc);   // .x coefficient, .y bits: tile Z mask
+    uint32_t *s_rs = (uint32_t *)(lbase + L.rs);   // [4][kLE] byte offsets of register coordinates
+    int32_t *s_bk = (int32_t *)(lbase + L.bk);     // bucket bounds
     __syncthreads();  // a previous call of this block may still read the arrays
     int halv = 0;
     if (MODE == 0) {
@@ -435,17 +420,19 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
         while (halv < 60 && ldexp(th, -halv) > 0.25) ++halv;
     }
     if (tid < 4 * kLE) s_rs[tid] = lds_slot(1u << pd.reg[tid / kLE][tid % kLE]) * 16u;
+    if (tid < 2 * kE + 1) s_bk[tid] = tid <= kE ? pd.bucket[tid] : 0;
     {
         const uint8_t *tb = ws + pd.term_off;
         const int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
         for (int k = tid; k < m; k += T_) {
-            zeta[k] = ((const uint32_t *)tb)[k];
-            ztile[k] = ((const uint64_t *)(tb + o2))[k];
-            coef[k] = ((const double *)(tb + o2 + 8 * (int64_t)m))[k];
+            const uint32_t z = ((const uint32_t *)tb)[k];
+            const uint64_t zt = ((const uint64_t *)(tb + o2))[k];
+            const double cf = ((const double *)(tb + o2 + 8 * (int64_t)m))[k];
+            trec[k] = make_double2(0.0, __longlong_as_double((long long)z));
+            tsrc[k] = make_double2(cf, __longlong_as_double((long long)zt));
         }
     }
     const double scale = pd.scale;
-    const int nrounds = nr > 0 ? nr : 1;
 
     // ---- per-thread constants (tile independent) ----
     // scatter/gather: element j of thread t is pivot pattern t + (j << TL)
@@ -528,14 +515,51 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     auto signs = [&](OFF xb) {
         const uint64_t xT = (uint64_t)xb / sizeof(T);
         for (int k = tid; k < m; k += T_) {
-            const double v = coef[k];
-            cks[k] = (__popcll(ztile[k] & xT) & 1) ? -v : v;
+            const double2 src = tsrc[k];
+            const uint64_t zt = (uint64_t)__double_as_longlong(src.y);
+            trec[k].x = (__popcll(zt & xT) & 1) ? -src.x : src.x;
         }
     };
     __syncthreads();
 
     auto transform = [&]() {
         double re[kE], im[kE];
+        auto read16 = [&](uint32_t cs, const uint32_t (&rs)[kLE]) {
+#pragma unroll
+            for (int jj = 0; jj < kE; ++jj) {
+                if (jj) cs ^= rs[__builtin_ctz(jj)];
+                const double2 a = lds_ld(cs);
+                re[jj ^ (jj >> 1)] = a.x;
+                im[jj ^ (jj >> 1)] = a.y;
+            }
+        };
+        auto write16 = [&](uint32_t cs, const uint32_t (&rs)[kLE]) {
+            asm volatile("" : "+v"(cs));
+#pragma unroll
+            for (int jj = 0; jj < kE; ++jj) {
+                if (jj) cs ^= rs[__builtin_ctz(jj)];
+                lds_st(cs, make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]));
+            }
+        };
+        // plain butterflies on register bits 1..nb-1 (they commute)
+        auto plain_rest = [&](int nb) {
+            switch (nb) {
+                case 4:
+                    bfly_fwd<1, false>(re, im);
+                    bfly_fwd<2, false>(re, im);
+                    bfly_fwd<3, false>(re, im);
+                    break;
+                case 3:
+                    bfly_fwd<1, false>(re, im);
+                    bfly_fwd<2, false>(re, im);
+                    break;
+                case 2:
+                    bfly_fwd<1, false>(re, im);
+                    break;
+                default:
+                    break;
+            }
+        };
         const int total = nr > 0 ? 2 * nr - 1 : 1;
         for (int step = 0; step < total; ++step) {
             const int r = step < nrounds ? step : 2 * nr - 2 - step;
@@ -547,47 +571,75 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             uint32_t rs[kLE];
 #pragma unroll
             for (int b = 0; b < kLE; ++b) rs[b] = s_rs[r * kLE + b];
-            {
-                uint32_t cs = ra;
-#pragma unroll
-                for (int jj = 0; jj < kE; ++jj) {
-                    if (jj) cs ^= rs[__builtin_ctz(jj)];
-                    const double2 a = lds_ld(cs);
-                    re[jj ^ (jj >> 1)] = a.x;
-                    im[jj ^ (jj >> 1)] = a.y;
-                }
-            }
             const int nb = __popc(pd.bmask[r]);
-            const uint32_t tw = pd.iflag[r];
-            if (lam) {
-                stages<true>(re, im, nb, tw);
-                // phi over the kE register patterns: bucket sums of the signed
-                // coefficients, then a kE-point Walsh-Hadamard of the sums
-                double A[kE];
+            if (!lam) {
+                // rounds other than Lambda's carry no twiddle: the forward and
+                // the inverse butterflies are the same plain (a + c, a - c)
+                read16(ra, rs);
+                bfly_fwd<0, false>(re, im);
+                if (GEN) {
+                    plain_rest(nb);
+                } else {
+                    bfly_fwd<1, false>(re, im);
+                    bfly_fwd<2, false>(re, im);
+                    bfly_fwd<3, false>(re, im);
+                }
+                write16(wa, rs);
+                __syncthreads();
+                continue;
+            }
+            read16(ra, rs);
+            const bool tw = pd.iflag[r] & 1u;
+            if (nb > 0) {
+                if (tw) bfly_fwd<0, true>(re, im);
+                else bfly_fwd<0, false>(re, im);
+                plain_rest(nb);
+            }
+            // phi over the kE register patterns: bucket sums of the signed
+            // coefficients, then a kE-point Walsh-Hadamard of the sums
+            double A[kE];
+            int bk[kE + 1];
 #pragma unroll
-                for (int w = 0; w < kE; ++w) {
-                    double sacc = 0.0;
-                    const int k1 = pd.bucket[w + 1];
-                    for (int k = pd.bucket[w]; k < k1; ++k) {
-                        const double ck = cks[k];
-                        sacc += (__popc(zeta[k] & sgnb) & 1) ? -ck : ck;
+            for (int w = 0; w <= kE; ++w) bk[w] = s_bk[w];
+#pragma unroll
+            for (int w = 0; w < kE; ++w) {
+                double sacc = 0.0;
+#pragma unroll 2
+                for (int k = bk[w]; k < bk[w + 1]; ++k) {
+                    const double2 rec = trec[k];
+                    const uint32_t z = (uint32_t)__double_as_longlong(rec.y);
+                    sacc += (__popc(z & sgnb) & 1) ? -rec.x : rec.x;
+                }
+                A[w] = sacc;
+            }
+#pragma unroll
+            for (int b = 0; b < kLE; ++b)
+#pragma unroll
+                for (int j = 0; j < kE; ++j)
+                    if (!((j >> b) & 1)) {
+                        const double a0 = A[j], a1 = A[j | (1 << b)];
+                        A[j] = a0 + a1;
+                        A[j | (1 << b)] = a0 - a1;
                     }
-                    A[w] = sacc;
+            if (MODE == 1) {
+#pragma unroll
+                for (int j = 0; j < kE; ++j) acc += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
+                break;
+            }
+            // (no double-angle steps is the common case: its own loop keeps
+            // the halving loop out of the per-amplitude code)
+            if (halv == 0) {
+#pragma unroll
+                for (int j = 0; j < kE; ++j) {
+                    double cc, ss;
+                    cis<FULL>(-tau * A[j], 0, cc, ss);
+                    cc *= scale;
+                    ss *= scale;
+                    const double ar = re[j], ai = im[j];
+                    re[j] = fma(ar, cc, -ai * ss);
+                    im[j] = fma(ar, ss, ai * cc);
                 }
-#pragma unroll
-                for (int b = 0; b < kLE; ++b)
-#pragma unroll
-                    for (int j = 0; j < kE; ++j)
-                        if (!((j >> b) & 1)) {
-                            const double a0 = A[j], a1 = A[j | (1 << b)];
-                            A[j] = a0 + a1;
-                            A[j | (1 << b)] = a0 - a1;
-                        }
-                if (MODE == 1) {
-#pragma unroll
-                    for (int j = 0; j < kE; ++j) acc += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
-                    break;
-                }
+            } else {
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
                     double cc, ss;
@@ -598,21 +650,13 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                     re[j] = fma(ar, cc, -ai * ss);
                     im[j] = fma(ar, ss, ai * cc);
                 }
-                stages<false>(re, im, nb, tw);
-            } else if (fwd) {
-                stages<true>(re, im, nb, tw);
-            } else {
-                stages<false>(re, im, nb, tw);
             }
-            {
-                uint32_t cs = wa;
-                asm volatile("" : "+v"(cs));
-#pragma unroll
-                for (int jj = 0; jj < kE; ++jj) {
-                    if (jj) cs ^= rs[__builtin_ctz(jj)];
-                    lds_st(cs, make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]));
-                }
+            if (nb > 0) {
+                plain_rest(nb);
+                if (tw) bfly_bwd<0, true>(re, im);
+                else bfly_bwd<0, false>(re, im);
             }
+            write16(wa, rs);
             __syncthreads();
         }
     };
@@ -631,9 +675,9 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     };
 
     int64_t ti = t0;
-    // complex128 tiles skip the register prefetch: it would not fit the
-    // register budget of two waves per SIMD
-    if (MODE == 0 && sizeof(T) == 8) {
+    // complex128 tiles and the general round code skip the register
+    // prefetch: it would not fit the register budget of two waves per SIMD
+    if (MODE == 0 && sizeof(T) == 8 && !GEN) {
         // Software pipeline.  The loop is rotated so that on every path into
         // the loop only the next tile's loads are outstanding; inside the body
         // the stores of the current tile are issued after them, so the wait
@@ -693,15 +737,16 @@ __device__ __forceinline__ double block_sum_waves(double acc, double *red) {
     return s2;
 }
 
-template <typename T, int MODE, typename OFF>
+template <typename T, int MODE, typename OFF, bool GEN>
 __global__ void __launch_bounds__(kMaxThreads)
 k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
        double tau, double *__restrict__ partial) {
     double acc = 0.0;
-    tile_pass<T, MODE, OFF>(state, pdp, ws, tau, blockIdx.x, pdp->n_tiles, gridDim.x, acc);
+    tile_pass<T, MODE, OFF, GEN>(state, pdp, ws, tau, blockIdx.x, pdp->n_tiles, gridDim.x, acc);
     if (MODE == 1) {
         extern __shared__ double2 lds_dyn[];
-        double *red = (double *)((char *)lds_dyn + tile_lds_bytes(pdp->D, blockDim.x) - 64);
+        const int nrounds = pdp->nr > 0 ? pdp->nr : 1;
+        double *red = (double *)((char *)lds_dyn + tile_lds(pdp->D, blockDim.x, nrounds, pdp->m).red);
         const double s2 = block_sum_waves(acc, red);
         if (threadIdx.x == 0) partial[blockIdx.x] += s2;
     }
@@ -719,7 +764,7 @@ struct MultiSeg {
     int64_t n_tiles;
 };
 
-template <typename T>
+template <typename T, bool GEN>
 __global__ void __launch_bounds__(kMaxThreads)
 k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
     const int64_t lo = (total * (int64_t)blockIdx.x) / gridDim.x;
@@ -730,7 +775,7 @@ k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
         const int64_t a = sg.first_item, b = sg.first_item + sg.n_tiles;
         const int64_t s0 = a > lo ? a : lo, s1 = b < hi ? b : hi;
         if (s0 >= s1) continue;
-        tile_pass<T, 0, uint32_t>((T *)sg.state, sg.pd, sg.ws, sg.tau, s0 - a, s1 - a, 1, acc);
+        tile_pass<T, 0, uint32_t, GEN>((T *)sg.state, sg.pd, sg.ws, sg.tau, s0 - a, s1 - a, 1, acc);
     }
 }
 
@@ -824,22 +869,28 @@ static void init_device_props() {
     set_lds(k_pass<float2, 1>, lds_generic);
     set_lds(k_pass<double2, 0>, lds_generic);
     set_lds(k_pass<double2, 1>, lds_generic);
-    const int lds = (int)tile_lds_bytes(kMaxTileLog2, kMaxThreads);
-    set_lds(k_tile<float2, 0, uint32_t>, lds);
-    set_lds(k_tile<float2, 1, uint32_t>, lds);
-    set_lds(k_tile<double2, 0, uint32_t>, lds);
-    set_lds(k_tile<double2, 1, uint32_t>, lds);
-    set_lds(k_tile<float2, 0, uint64_t>, lds);
-    set_lds(k_tile<float2, 1, uint64_t>, lds);
-    set_lds(k_tile<double2, 0, uint64_t>, lds);
-    set_lds(k_tile<double2, 1, uint64_t>, lds);
-    set_lds(k_tile_multi<float2>, lds);
-    set_lds(k_tile_multi<double2>, lds);
-    const bool ok = no_static_lds(k_tile<float2, 0, uint32_t>) && no_static_lds(k_tile<float2, 1, uint32_t>) &&
-                    no_static_lds(k_tile<double2, 0, uint32_t>) && no_static_lds(k_tile<double2, 1, uint32_t>) &&
-                    no_static_lds(k_tile<float2, 0, uint64_t>) && no_static_lds(k_tile<float2, 1, uint64_t>) &&
-                    no_static_lds(k_tile<double2, 0, uint64_t>) && no_static_lds(k_tile<double2, 1, uint64_t>) &&
-                    no_static_lds(k_tile_multi<float2>) && no_static_lds(k_tile_multi<double2>);
+    const int lds = (int)kTileLdsMax;
+    bool ok = true;
+    auto prep = [&](auto kernel) {
+        set_lds(kernel, lds);
+        ok = ok && no_static_lds(kernel);
+    };
+    prep(k_tile<float2, 0, uint32_t, false>);
+    prep(k_tile<float2, 0, uint32_t, true>);
+    prep(k_tile<double2, 0, uint32_t, false>);
+    prep(k_tile<double2, 0, uint32_t, true>);
+    prep(k_tile<float2, 0, uint64_t, false>);
+    prep(k_tile<float2, 0, uint64_t, true>);
+    prep(k_tile<double2, 0, uint64_t, false>);
+    prep(k_tile<double2, 0, uint64_t, true>);
+    prep(k_tile<float2, 1, uint32_t, true>);
+    prep(k_tile<double2, 1, uint32_t, true>);
+    prep(k_tile<float2, 1, uint64_t, true>);
+    prep(k_tile<double2, 1, uint64_t, true>);
+    prep(k_tile_multi<float2, false>);
+    prep(k_tile_multi<float2, true>);
+    prep(k_tile_multi<double2, false>);
+    prep(k_tile_multi<double2, true>);
     if (!ok) g_init_status = fail(SD_ERR_INTERNAL, "tile kernels were built with static LDS");
 }
 
@@ -869,16 +920,24 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
         // tiles of 2^13 fill one CU's LDS: one block per CU, next tile
         // prefetched into registers; smaller tiles run two or more blocks per CU
         const int per_cu = ph.D >= 13 ? 1 : 2;
-        const size_t lds_tile = tile_lds_bytes(ph.D, threads);
+        const size_t lds_tile = tile_lds(ph.D, threads, std::max(ph.nr, 1), (int)ph.terms.size()).total;
         const int g2 = MODE == 1 ? grid
                                  : (int)std::min<int64_t>(tiles, (int64_t)std::max(1, g_num_cu) * per_cu);
         // byte offsets inside the state fit 32 bits up to 4 GiB
         const bool narrow = ((uint64_t)sizeof(T) << p->n) <= ((uint64_t)1 << 32);
-        if (narrow)
-            hipLaunchKernelGGL((k_tile<T, MODE, uint32_t>), dim3(g2), dim3(threads), lds_tile, s,
+        // the expectation (MODE 1) always takes the general round code
+        const bool gen = MODE == 1 || !ph.full_rounds;
+        if (narrow && gen)
+            hipLaunchKernelGGL((k_tile<T, MODE, uint32_t, true>), dim3(g2), dim3(threads), lds_tile, s,
+                               (T *)state, pd, ws, tau, partial);
+        else if (narrow)
+            hipLaunchKernelGGL((k_tile<T, 0, uint32_t, false>), dim3(g2), dim3(threads), lds_tile, s,
+                               (T *)state, pd, ws, tau, partial);
+        else if (gen)
+            hipLaunchKernelGGL((k_tile<T, MODE, uint64_t, true>), dim3(g2), dim3(threads), lds_tile, s,
                                (T *)state, pd, ws, tau, partial);
         else
-            hipLaunchKernelGGL((k_tile<T, MODE, uint64_t>), dim3(g2), dim3(threads), lds_tile, s,
+            hipLaunchKernelGGL((k_tile<T, 0, uint64_t, false>), dim3(g2), dim3(threads), lds_tile, s,
                                (T *)state, pd, ws, tau, partial);
         return hip_check(hipGetLastError(), "k_tile launch");
     }
@@ -1169,6 +1228,8 @@ namespace {
 struct LevelLaunch {
     int64_t off, nseg, total;
     int D;
+    bool gen;       // some segment needs the general round code
+    uint32_t lds;   // largest LDS layout of its segments
 };
 
 // Build and upload the level tables of one step; instances with any tile
@@ -1197,12 +1258,15 @@ sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order
     launches->clear();
     for (int l = 0; l < levels; ++l) {
         for (int D = kTileMinD; D <= kMaxTileLog2; ++D) {
-            LevelLaunch L{(int64_t)host.size(), 0, 0, D};
+            LevelLaunch L{(int64_t)host.size(), 0, 0, D, false, 0};
             for (int i = 0; i < n_inst; ++i) {
                 if (is_small[i] || l >= (int)seq[i].size()) continue;
                 const sd_plan_t *p = e->plans[i];
                 const PassHost &ph = p->prog[e->dtype].passes[seq[i][l].first];
                 if (ph.D != D) continue;
+                if (!ph.full_rounds) L.gen = true;
+                L.lds = std::max(L.lds, tile_lds(D, 1 << (D - kLE), std::max(ph.nr, 1),
+                                                 (int)ph.terms.size()).total);
                 MultiSeg sg;
                 sg.state = states[i];
                 sg.ws = (const uint8_t *)p->ws;
@@ -1234,9 +1298,13 @@ sd_status launch_levels(sd_ensemble *e, const std::vector<LevelLaunch> &launches
         const int threads = 1 << (L.D - kLE);
         const int per_cu = L.D >= 13 ? 1 : 2;
         const int grid = (int)std::min<int64_t>(L.total, (int64_t)std::max(1, g_num_cu) * per_cu);
-        const size_t lds = tile_lds_bytes(L.D, threads);
-        hipLaunchKernelGGL((k_tile_multi<T>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
-                           (int)L.nseg, L.total);
+        const size_t lds = L.lds;
+        if (L.gen)
+            hipLaunchKernelGGL((k_tile_multi<T, true>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
+                               (int)L.nseg, L.total);
+        else
+            hipLaunchKernelGGL((k_tile_multi<T, false>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
+                               (int)L.nseg, L.total);
         sd_status r = hip_check(hipGetLastError(), "k_tile_multi launch");
         if (r != SD_OK) return r;
     }

@@ -57,12 +57,15 @@ struct Coords {
 // on-chip slots, like the CNOT network.  In the new basis
 //     q(M y') = sum_a d_a y'_a + 2 sum_{a<b} beta(f_a, f_b) y'_a y'_b   (mod 4)
 // with f_a the columns of M and d_a = q(f_a) in Z4.  Symplectic Gram-Schmidt
-// over GF(2) makes beta diagonal when some vector has beta(v, v) = 1, and
-// otherwise a sum of hyperbolic pairs; the chunk layout then keeps the two
-// vectors of every pair in different register chunks.  The kernel needs no
-// per-amplitude phase multiply then: an S (d_a odd) becomes a butterfly with
-// an i twiddle, a Z (d_a >= 2) and every cross-chunk CZ become a relabelling
-// of the butterfly outputs (see the register-round kernel).
+// over GF(2) splits the span into mutually orthogonal odd vectors
+// (beta(v, v) = 1), hyperbolic pairs (beta(v, x) = 1, both even) and a
+// radical; odd vectors are then traded for pairs until at most one is left.
+// The chunk layout keeps the two vectors of every pair in different register
+// chunks and puts the odd vector first in the last chunk.  The kernel needs
+// no per-amplitude phase multiply then: the one S (d_a odd) becomes a
+// butterfly with an i twiddle in the Lambda round, and every Z (d_a >= 2) and
+// cross-chunk CZ becomes a relabelling of butterfly outputs (see the
+// register-round kernel).
 namespace {
 
 int bil(const std::vector<uint32_t> &B, uint32_t x, uint32_t y) {
@@ -120,34 +123,61 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, std::vector<uint32
         }
         pairs.push_back({v, x});
     }
+    // At most one odd vector: three mutually orthogonal odd vectors e1, e2,
+    // e3 become the hyperbolic pair (e1+e2, e1+e3) and the odd e1+e2+e3
+    // (orthogonal to the pair); two become the odd e2 and the even e1+e2,
+    // whose only nonzero product is with e2 (its "partner").
+    while (dg.size() >= 3) {
+        const uint32_t e3 = dg.back();
+        dg.pop_back();
+        const uint32_t e2 = dg.back();
+        dg.pop_back();
+        const uint32_t e1 = dg.back();
+        dg.pop_back();
+        pairs.push_back({e1 ^ e2, e1 ^ e3});
+        dg.push_back(e1 ^ e2 ^ e3);
+    }
+    uint32_t odd = 0, partner = 0;
+    if (dg.size() == 2) {
+        odd = dg[1];
+        partner = dg[0] ^ dg[1];
+    } else if (dg.size() == 1) {
+        odd = dg[0];
+    }
+    // even vectors: the partner, first vectors of the pairs, the radical,
+    // second vectors of the pairs; packed greedily into chunks of up to
+    // kRegBits mutually orthogonal vectors
+    std::vector<uint32_t> ev;
+    if (partner) ev.push_back(partner);
+    for (auto &pr : pairs) ev.push_back(pr.first);
+    ev.insert(ev.end(), rad.begin(), rad.end());
+    for (auto &pr : pairs) ev.push_back(pr.second);
+    std::vector<std::vector<uint32_t>> ch;
+    for (uint32_t u : ev) {
+        bool fits = !ch.empty() && (int)ch.back().size() < kRegBits;
+        if (fits)
+            for (uint32_t w : ch.back())
+                if (bil(B, u, w)) fits = false;
+        if (!fits) ch.push_back({});
+        ch.back().push_back(u);
+    }
+    // the odd vector opens the last chunk (the Lambda round): its S is the
+    // only i twiddle of the pass
+    if (odd) {
+        bool fits = !ch.empty() && (int)ch.back().size() < kRegBits;
+        if (fits)
+            for (uint32_t w : ch.back())
+                if (bil(B, odd, w)) fits = false;
+        if (fits)
+            ch.back().insert(ch.back().begin(), odd);
+        else
+            ch.push_back({odd});
+    }
     f->clear();
     chunks->clear();
-    if (!dg.empty() || pairs.empty()) {
-        // diagonal: with an odd vector e every pair (v, x) turns into the odd,
-        // mutually orthogonal e+v+x, e+v, e+x
-        for (auto &pr : pairs) {
-            const uint32_t e = dg.back();
-            dg.back() = e ^ pr.first ^ pr.second;
-            dg.push_back(e ^ pr.first);
-            dg.push_back(e ^ pr.second);
-        }
-        *f = dg;
-        f->insert(f->end(), rad.begin(), rad.end());
-        for (int left = rho; left > 0; left -= kRegBits) chunks->push_back(std::min(left, kRegBits));
-        return;
-    }
-    // alternating: first vectors of the pairs, the radical, second vectors
-    const int p = (int)pairs.size();
-    for (auto &pr : pairs) f->push_back(pr.first);
-    f->insert(f->end(), rad.begin(), rad.end());
-    for (auto &pr : pairs) f->push_back(pr.second);
-    if (rho >= 2 * kRegBits) {
-        // a pair sits rho - p >= kRegBits positions apart: never in one chunk
-        for (int left = rho; left > 0; left -= kRegBits) chunks->push_back(std::min(left, kRegBits));
-    } else {
-        const int s0 = std::min(kRegBits, rho - p);
-        chunks->push_back(s0);
-        chunks->push_back(rho - s0);
+    for (auto &c : ch) {
+        f->insert(f->end(), c.begin(), c.end());
+        chunks->push_back((int)c.size());
     }
 }
 
@@ -216,6 +246,7 @@ sd_status plan_rounds(PassHost *ps) {
     PassHost &p = *ps;
     const int D = p.D, rho = p.rho;
     p.nr = 0;
+    p.full_rounds = true;
     for (int r = 0; r < 4; ++r) p.bmask[r] = p.iflag[r] = p.dflag[r] = p.later[r] = 0;
     const int RB = kRegBits;
     if (D < 2 * RB) {  // tiny tile: handled by the generic kernel only
@@ -247,6 +278,13 @@ sd_status plan_rounds(PassHost *ps) {
                 for (int b = off; b < rho; ++b) p.later[r] |= 1u << b;
             }
             p.lam_round = p.nr - 1;
+            p.full_rounds = true;
+            for (int r = 0; r < p.lam_round; ++r)
+                if (p.chunk[r] != RB) p.full_rounds = false;
+            // the kernel twiddles only register slot 0 of the Lambda round
+            for (int r = 0; r < p.nr; ++r)
+                if (p.iflag[r] & ~(r == p.lam_round ? 1u : 0u))
+                    return fail(SD_ERR_INTERNAL, "S outside slot 0 of the Lambda round");
         }
     }
     // sort the Lambda terms by their pattern on the Lambda round's registers

@@ -135,6 +135,7 @@ struct PassHost {
     uint32_t dflag[4] = {};         // register slots whose coordinate has a Z
     uint32_t later[4] = {};         // span coordinates of the chunks after r
     int lam_round = 0;              // chunk whose round applies Lambda
+    bool full_rounds = true;        // every chunk before lam_round is full
     std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
                                     // pattern on the registers of lam_round
 };

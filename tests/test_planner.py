@@ -323,7 +323,8 @@ def _export_all(p, dtype):
 
 
 def _check_round_structure(ps, rv):
-    """Chunks hold consecutive span coordinates and no CZ inside a chunk."""
+    """Chunks hold consecutive span coordinates and no CZ inside a chunk; the
+    only S sits in register slot 0 of the Lambda round."""
     rho, B = ps["rho"], [int(v) for v in ps["cz_s"]]
     nr = rv["n_rounds"]
     if rho == 0:
@@ -340,6 +341,8 @@ def _check_round_structure(ps, rv):
         for l, a in enumerate(coords):
             assert B[a] & cm & ~(1 << a) == 0, "CZ inside a register chunk"
             assert ((rv["iflag"][r] >> l) & 1) == ((B[a] >> a) & 1)
+            if (B[a] >> a) & 1:
+                assert r == nr - 1 and l == 0
             assert ((rv["dflag"][r] >> l) & 1) == ((ps["z_sign"] >> a) & 1)
         assert rv["later"][r] == sum(1 << b for b in range(len(seen), rho))
     assert seen == list(range(rho)) and rv["lam_round"] == nr - 1
@@ -362,8 +365,10 @@ def test_register_rounds_large_group_matches_oracle(seed, rho, alt):
     assert info.n_groups == 1
     passes, rounds = _export_all(p, sd.SD_C64)
     assert [q["rho"] for q in passes] == [rho]
-    off_diag = any(int(b) & ~(1 << i) for i, b in enumerate(passes[0]["cz_s"]))
-    assert off_diag == alt
+    # canonical form: exactly one S when the form is not alternating, none
+    # when it is
+    n_s = sum((int(b) >> i) & 1 for i, b in enumerate(passes[0]["cz_s"]))
+    assert n_s == (0 if alt else 1)
     for q, r in zip(passes, rounds):
         _check_round_structure(q, r)
     psi0 = workloads.random_state(n, 3)
