@@ -198,26 +198,46 @@ sd_status sd_plan_pass_count(const sd_plan_t *p, sd_dtype dt, int32_t *count);
 sd_status sd_plan_export_pass(const sd_plan_t *p, sd_dtype dt, int32_t i,
                               sd_pass_view *v);
 
-/* Register-round schedule of one tile pass (the on-chip Walsh-Hadamard of
-   the rho span coordinates runs in rounds of 4 coordinates held in
-   registers; see DESIGN notes of the tile kernel).  Chunk r holds span
-   coordinates in register slots 0..popcount(bmask[r])-1 and other tile
-   coordinates in the remaining slots; iflag/dflag mark slots whose
-   coordinate carries an S / a Z of the CZ/S layer; later[r] is the mask of
-   span coordinates of the chunks after r.  Lambda is applied in the round of
-   lam_round; terms (in the pass view's order) are grouped by their Lambda
-   pattern on that round's register slots: pattern w owns terms
-   bucket[w] .. bucket[w+1]-1.  Views stay valid until sd_plan_destroy.
+/* Register-round schedule of one tile pass.  The on-chip Walsh-Hadamard of
+   the rho span coordinates runs in rounds; a thread holds 16 amplitudes.
+   Round r transforms chunk r: its first coordinates sit in register slots
+   0..3 (reg[r]; only the low popcount(bmask[r]) slots are transformed, the
+   others carry filler coordinates), the next nx[r] on lane bits 4 and 5
+   (xl[r]); after the register butterflies register bits 2, 3 are exchanged
+   with lane bits 4, 5, leaving register coordinates regpost[r].  Lane bit i
+   of a thread is tile coordinate vector lanes[r][i] before the exchange and
+   lanes_post[r][i] after it; round 0 moves amplitudes between HBM and
+   registers directly, and its first io_coalesced lanes are the lowest
+   address bits.  iflag/dflag mark chunk slots (0..3 registers, 4..5 lanes)
+   whose coordinate carries an S / a Z of the CZ/S layer; later[r] is the
+   mask of span coordinates of the chunks after r.  Lambda is applied in the
+   round of lam_round; terms (in the pass view's order) are grouped by their
+   Lambda pattern on that round's registers after the exchange: pattern w owns
+   terms bucket[w] .. bucket[w+1]-1.  On-chip slot of tile coordinate t:
+   t ^ sum_j parity(t & swz[j]) << j.  Views stay valid until sd_plan_destroy.
    Errors: SD_ERR_ARG, SD_ERR_RANGE (pass index). */
 typedef struct {
     int32_t n_rounds;          /* chunks (0 when rho = 0: one Lambda round)    */
     int32_t lam_round;
     int32_t reg[4][4];
+    int32_t regpost[4][4];
+    int32_t xl[4][2];
+    int32_t nx[4];
     uint32_t bmask[4];
     uint32_t iflag[4];
     uint32_t dflag[4];
     uint32_t later[4];
     const int32_t *bucket;     /* 17 offsets                                    */
+    int32_t n_lanes;           /* D - 4                                         */
+    int32_t io_coalesced;
+    const uint32_t *lanes[4];
+    const uint32_t *lanes_post[4];
+    uint32_t swz[3];
+    int32_t staged;            /* 1: the tile moves between HBM and LDS in pivot
+                                  order (pivot_vec / pivot_coord of the pass
+                                  view) and round 0 reads it from LDS; used when
+                                  the lowest address bits cannot be round 0's
+                                  leading lanes                                */
 } sd_round_view;
 sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int32_t i,
                                 sd_round_view *v);

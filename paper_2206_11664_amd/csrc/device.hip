@@ -60,14 +60,27 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         d.nr = p.nr;
         d.lam_round = p.lam_round;
         for (int r = 0; r < 4; ++r) {
-            for (int b = 0; b < 4; ++b) d.reg[r][b] = p.reg[r][b];
+            for (int b = 0; b < 4; ++b) {
+                d.reg[r][b] = p.reg[r][b];
+                d.regpost[r][b] = p.regpost[r][b];
+            }
+            for (int x = 0; x < 2; ++x) d.xl[r][x] = p.xl[r][x];
+            d.nx[r] = p.nx[r];
             d.bmask[r] = p.bmask[r];
             d.iflag[r] = p.iflag[r];
             d.dflag[r] = p.dflag[r];
             d.later[r] = p.later[r];
+            for (size_t i = 0; i < p.lanes[r].size() && i < (size_t)kMaxD; ++i) {
+                d.lanes[r][i] = p.lanes[r][i];
+                d.lanes_post[r][i] = p.lanes_post[r][i];
+            }
         }
         for (int w = 0; w < 33; ++w) d.bucket[w] = p.bucket.empty() ? 0 : p.bucket[w];
         d.coef_abs_sum = p.coef_abs_sum;
+        for (size_t i = 0; i < p.io_phys.size() && i < (size_t)kMaxD; ++i) d.io_phys[i] = p.io_phys[i];
+        for (int l = 0; l < 4; ++l) d.io_reg[l] = p.io_reg[l];
+        for (int j = 0; j < 3; ++j) d.swz[j] = p.swz[j];
+        d.staged = p.staged ? 1 : 0;
         std::memcpy(buf.data() + i * sizeof(PassDev), &d, sizeof(d));
         uint8_t *t = buf.data() + toff;
         const int m = d.m;
@@ -238,12 +251,12 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
 // amplitudes of a thread differ in the kLE tile coordinates reg[r] and share
 // the others (taken from the thread index), so the butterflies of those
 // coordinates run in registers; between rounds the tile is exchanged through
-// LDS.  The LDS slot of tile coordinate t is t ^ fold(t >> 3) (fold = XOR of
-// its 3-bit groups): whenever the three lowest thread-index bits address three
-// adjacent coordinates, the 8 lanes of a 128-byte LDS phase hit distinct banks.
-// The slot map is linear over GF(2), so every address is a per-thread base
-// XOR a uniform offset; the tile sits at LDS address 0 and addresses are
-// plain byte offsets (no static LDS in these kernels).
+// LDS.  The LDS slot of tile coordinate t is t ^ sum_j parity(t & swz[j]) << j
+// with per-pass masks that the planner picks so that, in every round, the 8
+// lanes of a 128-byte LDS phase hit distinct banks.  The slot map is linear
+// over GF(2), so every address is a per-thread base XOR a uniform offset; the
+// tile sits at LDS address 0 and addresses are plain byte offsets (no static
+// LDS in these kernels).
 //
 // The CZ/S layer costs no per-amplitude work.  The planner puts its quadratic
 // form in a basis where no chunk has a CZ inside it, so the layer factors
@@ -274,18 +287,12 @@ __device__ __forceinline__ void lds_st(uint32_t a, double2 v) {
     *(lds_c2 *)(size_t)a = w;
 }
 
-__device__ __forceinline__ uint32_t lds_slot(uint32_t t) {
-    uint32_t h = t >> 3;
-    h ^= (h >> 3) ^ (h >> 6) ^ (h >> 9);
-    return t ^ (h & 7u);
-}
-
 // Dynamic LDS of k_tile, in bytes from 0: the tile (16 B per amplitude); per
 // thread and round the pair of round addresses (8 B); per term the record
 // {signed coefficient of the current tile, Lambda mask} (16 B) and the record
 // {coefficient, physical Z mask for the tile sign} (16 B); the register
-// offsets of the rounds (64 B); the 17 bucket bounds (80 B); 8 block-sum
-// slots (64 B).
+// offsets of the rounds before and after the lane exchange (128 B); the 17
+// bucket bounds (80 B); 8 block-sum slots (64 B).
 struct TileLds {
     uint32_t thr, trec, tsrc, rs, bk, red, total;
 };
@@ -295,14 +302,14 @@ __host__ __device__ inline TileLds tile_lds(int D, int threads, int nrounds, int
     l.trec = l.thr + 8u * (uint32_t)(nrounds * threads);
     l.tsrc = l.trec + 16u * (uint32_t)m;
     l.rs = l.tsrc + 16u * (uint32_t)m;
-    l.bk = l.rs + 64u;
+    l.bk = l.rs + 128u;
     l.red = l.bk + 80u;
     l.total = l.red + 64u;
     return l;
 }
 // the largest layout any pass can ask for (attribute setup)
 constexpr size_t kTileLdsMax =
-    ((size_t)16 << kMaxTileLog2) + 8 * 4 * (size_t)kMaxThreads + 32 * (size_t)kMaxPassTerms + 64 + 80 + 64;
+    ((size_t)16 << kMaxTileLog2) + 8 * 4 * (size_t)kMaxThreads + 32 * (size_t)kMaxPassTerms + 128 + 80 + 64;
 
 // e^{i theta}: Taylor polynomials of cos and sin at x = theta / 2^halv
 // (|x| <= 1/4), then halv double-angle steps.  FULL: degrees 12/13 (truncation
@@ -382,6 +389,45 @@ __device__ __forceinline__ void bfly_bwd(double (&re)[kE], double (&im)[kE]) {
         }
 }
 
+// Exchange register bit B with lane bit LB (4 or 5) inside the wave: for
+// every register pair differing in bit B, a 2x2 transpose between the pair
+// and the two lane halves, so that afterwards register bit B indexes the
+// coordinate lane bit LB held and lane bit LB the one register bit B held.
+template <int LB>
+__device__ __forceinline__ void lane_swap(double &x, double &y) {
+    const uint64_t ux = (uint64_t)__double_as_longlong(x), uy = (uint64_t)__double_as_longlong(y);
+    const uint32_t xl = (uint32_t)ux, xh = (uint32_t)(ux >> 32);
+    const uint32_t yl = (uint32_t)uy, yh = (uint32_t)(uy >> 32);
+    uint32_t nxl, nyl, nxh, nyh;
+    if (LB == 4) {
+        const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        nxl = l[0];
+        nyl = l[1];
+        nxh = h[0];
+        nyh = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        nxl = l[0];
+        nyl = l[1];
+        nxh = h[0];
+        nyh = h[1];
+    }
+    x = __longlong_as_double((long long)(((uint64_t)nxh << 32) | nxl));
+    y = __longlong_as_double((long long)(((uint64_t)nyh << 32) | nyl));
+}
+
+template <int B, int LB>
+__device__ __forceinline__ void exch(double (&re)[kE], double (&im)[kE]) {
+#pragma unroll
+    for (int j = 0; j < kE; ++j)
+        if (!((j >> B) & 1)) {
+            lane_swap<LB>(re[j], re[j | (1 << B)]);
+            lane_swap<LB>(im[j], im[j | (1 << B)]);
+        }
+}
+
 __device__ __forceinline__ double2 to_c128(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ __forceinline__ double2 to_c128(double2 v) { return v; }
 __device__ __forceinline__ void from_c128(float2 &o, double2 v) { o = make_float2((float)v.x, (float)v.y); }
@@ -395,14 +441,22 @@ __device__ __forceinline__ void from_c128(double2 &o, double2 v) { o = v; }
 // coordinates in rounds other than Lambda's; without it those rounds are
 // straight-line code (four plain butterfly stages between one LDS read and
 // one LDS write).
+//
+// Round 0 reads its amplitudes straight from HBM into registers (its lanes
+// run over the lowest address bits) and its mirrored inverse round writes
+// them straight back, so the tile crosses LDS only between rounds; a pass of
+// a single round never touches LDS for amplitudes.
 template <typename T, int MODE, typename OFF, bool GEN>
 __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *__restrict__ pdp,
                                           const uint8_t *__restrict__ ws, double tau, int64_t t0,
                                           int64_t t1, int64_t stride, double &acc) {
     constexpr bool FULL = sizeof(T) == 16;
+    // complex128 tiles and the general round code skip the register
+    // prefetch of the next tile: it would not fit two waves per SIMD
+    constexpr bool PF = MODE == 0 && sizeof(T) == 8 && !GEN;
     extern __shared__ double2 lds_dyn[];
     const PassDev &pd = *pdp;
-    const int D = pd.D, TL = D - kLE, c = pd.c, m = pd.m, nr = pd.nr;
+    const int D = pd.D, TL = D - kLE, m = pd.m, nr = pd.nr;
     const uint32_t T_ = blockDim.x;
     const uint32_t tid = threadIdx.x;
     char *lbase = (char *)lds_dyn;
@@ -412,6 +466,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     double2 *trec = (double2 *)(lbase + L.trec);   // .x signed coefficient, .y bits: Lambda mask
     double2 *tsrc = (double2 *)(lbase + L.tsrc);   // .x coefficient, .y bits: tile Z mask
     uint32_t *s_rs = (uint32_t *)(lbase + L.rs);   // [4][kLE] byte offsets of register coordinates
+    uint32_t *s_ws = s_rs + 4 * kLE;               // the same after the lane exchange
     int32_t *s_bk = (int32_t *)(lbase + L.bk);     // bucket bounds
     __syncthreads();  // a previous call of this block may still read the arrays
     int halv = 0;
@@ -419,7 +474,15 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
         const double th = fabs(tau) * pd.coef_abs_sum;
         while (halv < 60 && ldexp(th, -halv) > 0.25) ++halv;
     }
-    if (tid < 4 * kLE) s_rs[tid] = lds_slot(1u << pd.reg[tid / kLE][tid % kLE]) * 16u;
+    const uint32_t sw0 = pd.swz[0], sw1 = pd.swz[1], sw2 = pd.swz[2];
+    auto slot = [&](uint32_t t) {
+        return t ^ ((uint32_t)(__popc(t & sw0) & 1) | ((uint32_t)(__popc(t & sw1) & 1) << 1) |
+                    ((uint32_t)(__popc(t & sw2) & 1) << 2));
+    };
+    if (tid < 4 * kLE) {
+        s_rs[tid] = slot(1u << pd.reg[tid / kLE][tid % kLE]) * 16u;
+        s_ws[tid] = slot(1u << pd.regpost[tid / kLE][tid % kLE]) * 16u;
+    }
     if (tid < 2 * kE + 1) s_bk[tid] = tid <= kE ? pd.bucket[tid] : 0;
     {
         const uint8_t *tb = ws + pd.term_off;
@@ -435,57 +498,74 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     const double scale = pd.scale;
 
     // ---- per-thread constants (tile independent) ----
-    // scatter/gather: element j of thread t is pivot pattern t + (j << TL)
+    // round 0: lane bit i is tile coordinate vector lanes[0][i] (physical
+    // offset io_phys[i]); register slot l is coordinate reg[0][l] (offset
+    // io_reg[l])
+    // A staged pass moves the tile in pivot order instead: element j of
+    // thread t is pivot pattern t + (j << TL), at LDS slot of tile
+    // coordinate sum mr[i] over its pivot bits.
+    const bool staged = pd.staged != 0;
+    const int c = pd.c;
     OFF off_t = 0;
-    uint32_t tc_t = 0;
-    for (int i = 0; i < TL; ++i)
-        if ((tid >> i) & 1) {
-            off_t ^= (OFF)(i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]) * (OFF)sizeof(T);
-            tc_t ^= pd.mr[i];
-        }
-    const uint32_t sl_t = lds_slot(tc_t) * 16u;
-    // uniform increments of the Gray-code address walks over the kE elements
     OFF pv[kLE];
-    uint32_t sv[kLE];
+    uint32_t sl_t = 0, sv[kLE];
+    if (!staged) {
+        for (int i = 0; i < TL; ++i)
+            if ((tid >> i) & 1) off_t ^= (OFF)pd.io_phys[i] * (OFF)sizeof(T);
 #pragma unroll
-    for (int b = 0; b < kLE; ++b) {
-        const int i = TL + b;
-        pv[b] = (OFF)(i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]) * (OFF)sizeof(T);
-        sv[b] = lds_slot(pd.mr[i]) * 16u;
+        for (int b = 0; b < kLE; ++b) {
+            pv[b] = (OFF)pd.io_reg[b] * (OFF)sizeof(T);
+            sv[b] = 0;
+        }
+    } else {
+        uint32_t tc_t = 0;
+        for (int i = 0; i < TL; ++i)
+            if ((tid >> i) & 1) {
+                off_t ^= (OFF)(i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]) * (OFF)sizeof(T);
+                tc_t ^= pd.mr[i];
+            }
+        sl_t = slot(tc_t) * 16u;
+#pragma unroll
+        for (int b = 0; b < kLE; ++b) {
+            const int i = TL + b;
+            pv[b] = (OFF)(i < c ? ((uint64_t)1 << i) : pd.u_hi[i - c]) * (OFF)sizeof(T);
+            sv[b] = slot(pd.mr[i]) * 16u;
+        }
     }
-    // rounds: thread-index bits fill the tile coordinates outside reg[r],
-    // lowest first.  thr[r] = (address the forward round reads, address it
-    // writes); the second carries the thread's output XOR.
+    // thr[r] = (address the forward round reads, before the lane exchange;
+    // address it writes, after the exchange, with the thread's output XOR)
     uint32_t sgnb = 0;  // tile coordinates for the signs of Lambda's terms
     for (int r = 0; r < nrounds; ++r) {
-        uint32_t regm = 0;
-        for (int b = 0; b < kLE; ++b) regm |= 1u << pd.reg[r][b];
-        uint32_t bt = 0;
-        int i = 0;
-        for (int q = 0; q < D; ++q)
-            if (!((regm >> q) & 1)) {
-                bt |= ((tid >> i) & 1u) << q;
-                ++i;
+        uint32_t bt = 0, btp = 0;
+        for (int i = 0; i < TL; ++i)
+            if ((tid >> i) & 1) {
+                bt ^= pd.lanes[r][i];
+                btp ^= pd.lanes_post[r][i];
             }
         uint32_t pm = 0;
-        for (int l = 0; l < kLE; ++l)
-            if ((pd.bmask[r] >> l) & 1u) {
-                const int a = pd.reg[r][l];
-                const uint32_t bit = (__popc(pd.B[a] & pd.later[r] & bt) ^ (pd.dflag[r] >> l)) & 1u;
-                pm |= bit << a;
+        for (int l = 0; l < kLE + 2; ++l) {
+            int a = -1;
+            if (l < kLE) {
+                if ((pd.bmask[r] >> l) & 1u) a = pd.reg[r][l];
+            } else if (l - kLE < pd.nx[r]) {
+                a = pd.xl[r][l - kLE];
             }
-        const uint32_t rd = lds_slot(bt) * 16u;
+            if (a < 0) continue;
+            const uint32_t bit = (__popc(pd.B[a] & pd.later[r] & bt) ^ (pd.dflag[r] >> l)) & 1u;
+            pm |= bit << a;
+        }
+        const uint32_t rd = slot(bt) * 16u;
         if (r == nrounds - 1) {
-            sgnb = bt ^ pm;
+            sgnb = btp ^ pm;
             thr[r * T_ + tid] = make_uint2(rd, rd);
         } else {
-            thr[r * T_ + tid] = make_uint2(rd, lds_slot(bt ^ pm) * 16u);
+            thr[r * T_ + tid] = make_uint2(rd, slot(btp ^ pm) * 16u);
         }
     }
 
-    // Element address = tile base XOR in-tile offset (the pivot vectors may
-    // have bits at free positions, so the two are not added).  Offsets are in
-    // bytes from the state pointer.
+    // Element address = tile base XOR in-tile offset (the lane and register
+    // vectors may have bits at free positions, so the two are not added).
+    // Offsets are in bytes from the state pointer.
     T pre[kE];
     const char *sbase = (const char *)state;
     auto tile_off = [&](int64_t ti) {
@@ -494,22 +574,14 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             if ((ti >> i) & 1) xT |= (uint64_t)1 << pd.free_pos[i];
         return (OFF)xT * (OFF)sizeof(T);
     };
+    // round 0's amplitudes of tile xb into pre[] (register index order)
     auto load_tile = [&](OFF xb) {
         OFF co = xb ^ off_t;
         asm volatile("" : "+v"(co));
 #pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            if (j) co ^= pv[__builtin_ctz(j)];
-            pre[j] = *(const T *)(sbase + co);
-        }
-    };
-    auto scatter = [&]() {
-        uint32_t cs = sl_t;
-        asm volatile("" : "+v"(cs));
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            if (j) cs ^= sv[__builtin_ctz(j)];
-            lds_st(cs, to_c128(pre[j]));
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) co ^= pv[__builtin_ctz(jj)];
+            pre[jj ^ (jj >> 1)] = *(const T *)(sbase + co);
         }
     };
     auto signs = [&](OFF xb) {
@@ -520,80 +592,187 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             trec[k].x = (__popcll(zt & xT) & 1) ? -src.x : src.x;
         }
     };
-    __syncthreads();
 
-    auto transform = [&]() {
-        double re[kE], im[kE];
-        auto read16 = [&](uint32_t cs, const uint32_t (&rs)[kLE]) {
+    double re[kE], im[kE];
+    auto read16 = [&](uint32_t cs, const uint32_t (&rs)[kLE]) {
 #pragma unroll
-            for (int jj = 0; jj < kE; ++jj) {
-                if (jj) cs ^= rs[__builtin_ctz(jj)];
-                const double2 a = lds_ld(cs);
-                re[jj ^ (jj >> 1)] = a.x;
-                im[jj ^ (jj >> 1)] = a.y;
-            }
-        };
-        auto write16 = [&](uint32_t cs, const uint32_t (&rs)[kLE]) {
-            asm volatile("" : "+v"(cs));
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) cs ^= rs[__builtin_ctz(jj)];
+            const double2 a = lds_ld(cs);
+            re[jj ^ (jj >> 1)] = a.x;
+            im[jj ^ (jj >> 1)] = a.y;
+        }
+    };
+    auto write16 = [&](uint32_t cs, const uint32_t (&rs)[kLE]) {
+        asm volatile("" : "+v"(cs));
 #pragma unroll
-            for (int jj = 0; jj < kE; ++jj) {
-                if (jj) cs ^= rs[__builtin_ctz(jj)];
-                lds_st(cs, make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]));
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) cs ^= rs[__builtin_ctz(jj)];
+            lds_st(cs, make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]));
+        }
+    };
+    auto from_pre = [&]() {
+#pragma unroll
+        for (int g = 0; g < kE; ++g) {
+            const double2 a = to_c128(pre[g]);
+            re[g] = a.x;
+            im[g] = a.y;
+        }
+    };
+    // without the prefetch, round 0's amplitudes go straight into re/im
+    auto load_regs = [&](OFF xb) {
+        OFF co = xb ^ off_t;
+        asm volatile("" : "+v"(co));
+#pragma unroll
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) co ^= pv[__builtin_ctz(jj)];
+            const double2 a = to_c128(*(const T *)(sbase + co));
+            re[jj ^ (jj >> 1)] = a.x;
+            im[jj ^ (jj >> 1)] = a.y;
+        }
+    };
+    auto store16 = [&](OFF xb) {
+        OFF co = xb ^ off_t;
+        asm volatile("" : "+v"(co));
+#pragma unroll
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) co ^= pv[__builtin_ctz(jj)];
+            const int g = jj ^ (jj >> 1);
+            from_c128(*(T *)((char *)state + co), make_double2(re[g], im[g]));
+        }
+    };
+    // staging of a staged pass (pivot order, Gray walk over the slots)
+    auto scatter_pre = [&]() {
+        uint32_t cs = sl_t;
+        asm volatile("" : "+v"(cs));
+#pragma unroll
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) cs ^= sv[__builtin_ctz(jj)];
+            lds_st(cs, to_c128(pre[jj ^ (jj >> 1)]));
+        }
+    };
+    auto scatter_regs = [&]() {
+        uint32_t cs = sl_t;
+        asm volatile("" : "+v"(cs));
+#pragma unroll
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) cs ^= sv[__builtin_ctz(jj)];
+            lds_st(cs, make_double2(re[jj ^ (jj >> 1)], im[jj ^ (jj >> 1)]));
+        }
+    };
+    auto gather = [&](OFF xb) {
+        uint32_t cs = sl_t;
+        OFF co = xb ^ off_t;
+        asm volatile("" : "+v"(cs), "+v"(co));
+#pragma unroll
+        for (int jj = 0; jj < kE; ++jj) {
+            if (jj) {
+                cs ^= sv[__builtin_ctz(jj)];
+                co ^= pv[__builtin_ctz(jj)];
             }
-        };
-        // plain butterflies on register bits 1..nb-1 (they commute)
-        auto plain_rest = [&](int nb) {
-            switch (nb) {
-                case 4:
-                    bfly_fwd<1, false>(re, im);
-                    bfly_fwd<2, false>(re, im);
-                    bfly_fwd<3, false>(re, im);
-                    break;
-                case 3:
-                    bfly_fwd<1, false>(re, im);
-                    bfly_fwd<2, false>(re, im);
-                    break;
-                case 2:
-                    bfly_fwd<1, false>(re, im);
-                    break;
-                default:
-                    break;
-            }
-        };
+            from_c128(*(T *)((char *)state + co), lds_ld(cs));
+        }
+    };
+    // plain butterflies on register bits 1..nb-1 (they commute)
+    auto plain_rest = [&](int nb) {
+        switch (nb) {
+            case 4:
+                bfly_fwd<1, false>(re, im);
+                bfly_fwd<2, false>(re, im);
+                bfly_fwd<3, false>(re, im);
+                break;
+            case 3:
+                bfly_fwd<1, false>(re, im);
+                bfly_fwd<2, false>(re, im);
+                break;
+            case 2:
+                bfly_fwd<1, false>(re, im);
+                break;
+            default:
+                break;
+        }
+    };
+
+    // The rounds of one tile.  Step 0 takes its input from pre[] and, with
+    // PF, then refills pre[] with the next tile's round-0 amplitudes; the
+    // last step stores to HBM.  Every step ends with a block barrier.
+    // exchange of register bits 2, 3 with lane bits 4, 5 (nx of them), and
+    // butterflies on register bits 2, 3 (nx of them)
+    auto xchg = [&](int nx) {
+        if (nx >= 1) exch<2, 4>(re, im);
+        if (nx == 2) exch<3, 5>(re, im);
+    };
+    auto stages_x = [&](int nx) {
+        if (nx >= 1) bfly_fwd<2, false>(re, im);
+        if (nx == 2) bfly_fwd<3, false>(re, im);
+    };
+
+    // The rounds of one tile.  A round other than Lambda's runs butterflies
+    // on register bits 0..3, exchanges bits 2, 3 with lane bits 4, 5, and runs
+    // butterflies on bits 2, 3 again: forward (from the layout before the
+    // exchange) that transforms the register coordinates, then the exchanged
+    // ones; backward (from the layout after it) the same sequence transforms
+    // the exchanged coordinates first.  Butterflies on different coordinates
+    // commute and carry no twiddle outside the Lambda round, so both
+    // directions are the same code.  Step 0 takes its input from pre[] (or
+    // from re/im loaded before) and, with PF, then refills pre[] with the next
+    // tile's round-0 amplitudes; the last step stores to HBM.  Every step ends
+    // with a block barrier.
+    auto transform = [&](OFF xb, bool pf_next, OFF xb_next) {
         const int total = nr > 0 ? 2 * nr - 1 : 1;
         for (int step = 0; step < total; ++step) {
             const int r = step < nrounds ? step : 2 * nr - 2 - step;
             const bool lam = step == nrounds - 1;
             const bool fwd = step < nrounds - 1;
+            const bool last = step == total - 1;
             const uint2 ab = thr[r * T_ + tid];
             const uint32_t ra = fwd || lam ? ab.x : ab.y;
             const uint32_t wa = fwd ? ab.y : ab.x;
-            uint32_t rs[kLE];
+            // uniform register offsets of the layouts read and written
+            uint32_t rin[kLE], rout[kLE];
 #pragma unroll
-            for (int b = 0; b < kLE; ++b) rs[b] = s_rs[r * kLE + b];
+            for (int b = 0; b < kLE; ++b) {
+                const uint32_t pre_off = s_rs[r * kLE + b], post_off = s_ws[r * kLE + b];
+                rin[b] = fwd || lam ? pre_off : post_off;
+                rout[b] = fwd ? post_off : pre_off;
+            }
             const int nb = __popc(pd.bmask[r]);
+            const int nx = pd.nx[r];
+            if (step == 0 && !staged) {
+                if (PF) {
+                    from_pre();
+                    if (pf_next) load_tile(xb_next);
+                }
+            } else {
+                read16(ra, rin);
+            }
             if (!lam) {
-                // rounds other than Lambda's carry no twiddle: the forward and
-                // the inverse butterflies are the same plain (a + c, a - c)
-                read16(ra, rs);
                 bfly_fwd<0, false>(re, im);
                 if (GEN) {
                     plain_rest(nb);
+                    xchg(nx);
+                    stages_x(nx);
                 } else {
                     bfly_fwd<1, false>(re, im);
                     bfly_fwd<2, false>(re, im);
                     bfly_fwd<3, false>(re, im);
+                    exch<2, 4>(re, im);
+                    exch<3, 5>(re, im);
+                    bfly_fwd<2, false>(re, im);
+                    bfly_fwd<3, false>(re, im);
                 }
-                write16(wa, rs);
+                if (last && !staged) store16(xb);
+                else write16(wa, rout);
                 __syncthreads();
                 continue;
             }
-            read16(ra, rs);
             const bool tw = pd.iflag[r] & 1u;
             if (nb > 0) {
                 if (tw) bfly_fwd<0, true>(re, im);
                 else bfly_fwd<0, false>(re, im);
                 plain_rest(nb);
+                xchg(nx);
+                stages_x(nx);
             }
             // phi over the kE register patterns: bucket sums of the signed
             // coefficients, then a kE-point Walsh-Hadamard of the sums
@@ -624,6 +803,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             if (MODE == 1) {
 #pragma unroll
                 for (int j = 0; j < kE; ++j) acc += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
+                __syncthreads();
                 break;
             }
             // (no double-angle steps is the common case: its own loop keeps
@@ -652,75 +832,55 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                 }
             }
             if (nb > 0) {
+                stages_x(nx);
+                xchg(nx);
                 plain_rest(nb);
                 if (tw) bfly_bwd<0, true>(re, im);
                 else bfly_bwd<0, false>(re, im);
             }
-            write16(wa, rs);
+            if (last && !staged) store16(xb);
+            else write16(wa, rout);
             __syncthreads();
-        }
-    };
-    auto gather = [&](OFF xb) {
-        uint32_t cs = sl_t;
-        OFF co = xb ^ off_t;
-        asm volatile("" : "+v"(cs), "+v"(co));
-#pragma unroll
-        for (int j = 0; j < kE; ++j) {
-            if (j) {
-                cs ^= sv[__builtin_ctz(j)];
-                co ^= pv[__builtin_ctz(j)];
-            }
-            from_c128(*(T *)((char *)state + co), lds_ld(cs));
         }
     };
 
-    int64_t ti = t0;
-    // complex128 tiles and the general round code skip the register
-    // prefetch: it would not fit the register budget of two waves per SIMD
-    if (MODE == 0 && sizeof(T) == 8 && !GEN) {
-        // Software pipeline.  The loop is rotated so that on every path into
-        // the loop only the next tile's loads are outstanding; inside the body
-        // the stores of the current tile are issued after them, so the wait
-        // for the next tile's data before its scatter does not wait for the
-        // stores (one counter tracks both, in issue order).
-        if (ti < t1) {
-            OFF tp_cur = tile_off(ti);
-            load_tile(tp_cur);
-            scatter();
-            signs(tp_cur);
-            int64_t tn = ti + stride;
-            OFF tp_next = tp_cur;
-            if (tn < t1) {
-                tp_next = tile_off(tn);
-                load_tile(tp_next);
+    __syncthreads();
+    if (PF) {
+        // Software pipeline: step 0 of tile t issues the loads of tile t +
+        // stride right after consuming its own, so they overlap the rest of
+        // tile t; the stores of tile t are issued after them (one counter
+        // tracks loads and stores in issue order, so waiting for the next
+        // tile's loads does not wait for these stores).
+        // A staged pass scatters pre[] to LDS first and issues the next
+        // loads right after that.
+        if (t0 < t1) load_tile(tile_off(t0));
+        for (int64_t ti = t0; ti < t1; ti += stride) {
+            const OFF xb = tile_off(ti);
+            const int64_t tn = ti + stride;
+            signs(xb);
+            if (staged) {
+                scatter_pre();
+                if (tn < t1) load_tile(tile_off(tn));
             }
             __syncthreads();
-            while (true) {
-                transform();
-                gather(tp_cur);
-                __syncthreads();
-                if (tn >= t1) break;
-                tp_cur = tp_next;
-                scatter();
-                signs(tp_cur);
-                tn += stride;
-                if (tn < t1) {
-                    tp_next = tile_off(tn);
-                    load_tile(tp_next);
-                }
+            transform(xb, tn < t1, tn < t1 ? tile_off(tn) : (OFF)0);
+            if (staged) {
+                if (MODE == 0) gather(xb);
                 __syncthreads();
             }
         }
     } else {
-        for (; ti < t1; ti += stride) {
-            const OFF tp = tile_off(ti);
-            load_tile(tp);
-            scatter();
-            signs(tp);
+        for (int64_t ti = t0; ti < t1; ti += stride) {
+            const OFF xb = tile_off(ti);
+            load_regs(xb);
+            signs(xb);
+            if (staged) scatter_regs();
             __syncthreads();
-            transform();
-            if (MODE == 0) gather(tp);
-            __syncthreads();
+            transform(xb, false, (OFF)0);
+            if (staged) {
+                if (MODE == 0) gather(xb);
+                __syncthreads();
+            }
         }
     }
 }
@@ -894,6 +1054,14 @@ static void init_device_props() {
     if (!ok) g_init_status = fail(SD_ERR_INTERNAL, "tile kernels were built with static LDS");
 }
 
+// Resident blocks of k_tile per CU: the kernel needs up to 256 VGPRs per
+// lane, i.e. two waves per SIMD, eight per CU; a tile of 2^D amplitudes has
+// 2^(D-4) threads.  (The LDS of that many tiles fits in 160 KB.)
+static int blocks_per_cu(int D) {
+    const int waves = std::max(1, (1 << (D - kLE)) / 64);
+    return std::max(1, 8 / waves);
+}
+
 static int grid_for(int64_t tiles) {
     std::call_once(g_once, init_device_props);
     int cap = std::max(1, g_num_cu) * 2;
@@ -919,7 +1087,7 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
         const int threads = 1 << (ph.D - kLE);
         // tiles of 2^13 fill one CU's LDS: one block per CU, next tile
         // prefetched into registers; smaller tiles run two or more blocks per CU
-        const int per_cu = ph.D >= 13 ? 1 : 2;
+        const int per_cu = blocks_per_cu(ph.D);
         const size_t lds_tile = tile_lds(ph.D, threads, std::max(ph.nr, 1), (int)ph.terms.size()).total;
         const int g2 = MODE == 1 ? grid
                                  : (int)std::min<int64_t>(tiles, (int64_t)std::max(1, g_num_cu) * per_cu);
@@ -1296,7 +1464,7 @@ sd_status launch_levels(sd_ensemble *e, const std::vector<LevelLaunch> &launches
     const MultiSeg *dsegs = (const MultiSeg *)e->ws;
     for (auto &L : launches) {
         const int threads = 1 << (L.D - kLE);
-        const int per_cu = L.D >= 13 ? 1 : 2;
+        const int per_cu = blocks_per_cu(L.D);
         const int grid = (int)std::min<int64_t>(L.total, (int64_t)std::max(1, g_num_cu) * per_cu);
         const size_t lds = L.lds;
         if (L.gen)

@@ -26,13 +26,23 @@ struct alignas(256) PassDev {
     // register-round schedule (k_tile), one entry per chunk
     int32_t nr;             // chunks of span coordinates (0 when rho = 0)
     int32_t lam_round;      // chunk whose round applies Lambda
-    int32_t reg[4][4];      // tile coordinates in registers per chunk
+    int32_t reg[4][4];      // tile coordinates in register slots per chunk
+    int32_t regpost[4][4];  // register coordinates after the lane exchange
+    int32_t xl[4][2];       // chunk coordinates on lane bits 4, 5
+    int32_t nx[4];          // how many of them are exchanged (0..2)
     uint32_t bmask[4];      // register slots that get butterflies (low bits)
     uint32_t iflag[4];      // slots whose coordinate carries an S (i twiddle)
-    uint32_t dflag[4];      // slots whose coordinate carries a Z
+    uint32_t dflag[4];      // chunk slots (0..3 registers, 4..5 lanes) with a Z
     uint32_t later[4];      // span coordinates of the chunks after this one
-    int32_t bucket[33];     // term offsets by Lambda pattern on reg[lam_round]
+    int32_t bucket[33];     // term offsets by Lambda pattern on regpost[lam_round]
     double coef_abs_sum;    // sum |coef| of the pass
+    uint32_t lanes[4][kMaxD];       // tile coordinates of lane bits per round
+    uint32_t lanes_post[4][kMaxD];  // the same after the lane exchange
+    uint64_t io_phys[kMaxD];        // physical offsets of round 0's lane bits
+    uint64_t io_reg[4];             // physical offsets of round 0's register slots
+    uint32_t swz[3];                // LDS slot of t: t ^ sum_j parity(t & swz[j]) << j
+    int32_t staged;                 // round 0 reads the tile from LDS, staged in
+                                    // pivot order (u_hi, mr), not from HBM
 };
 
 // term arrays at term_off: uint32 zeta[m]; (pad to 8) uint64 ztile[m]; double coef[m]

@@ -203,13 +203,24 @@ extern "C" sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int3
     v->n_rounds = h.nr;
     v->lam_round = h.lam_round;
     for (int r = 0; r < 4; ++r) {
-        for (int b = 0; b < 4; ++b) v->reg[r][b] = h.reg[r][b];
+        for (int b = 0; b < 4; ++b) {
+            v->reg[r][b] = h.reg[r][b];
+            v->regpost[r][b] = h.regpost[r][b];
+        }
+        for (int x = 0; x < 2; ++x) v->xl[r][x] = h.xl[r][x];
+        v->nx[r] = h.nx[r];
         v->bmask[r] = h.bmask[r];
         v->iflag[r] = h.iflag[r];
         v->dflag[r] = h.dflag[r];
         v->later[r] = h.later[r];
+        v->lanes[r] = h.lanes[r].data();
+        v->lanes_post[r] = h.lanes_post[r].data();
     }
     v->bucket = h.bucket.data();
+    v->n_lanes = (int32_t)h.lanes[0].size();
+    v->io_coalesced = h.io_k;
+    for (int j = 0; j < 3; ++j) v->swz[j] = h.swz[j];
+    v->staged = h.staged ? 1 : 0;
     return SD_OK;
 }
 

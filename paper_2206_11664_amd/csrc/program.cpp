@@ -22,6 +22,7 @@
 // A group whose tile would exceed the on-chip limit is split into commuting
 // sub-groups (any split is exact: the terms commute), each with its own tile.
 #include <algorithm>
+#include <array>
 #include <cmath>
 
 #include "device_types.h"
@@ -81,8 +82,14 @@ int qform(const std::vector<uint32_t> &B, uint32_t x) {
 }
 
 // new span basis f (old coordinates, in final order) and chunk sizes
-void canonical_basis(const std::vector<uint32_t> &B, int rho, std::vector<uint32_t> *f,
-                     std::vector<int> *chunks) {
+// lowspan: span parts (old coordinates) of the tile coordinates of the
+// lowest address bits; the chunk of round 0, which moves the tile between HBM
+// and registers, is built from basis vectors none of them depends on (see
+// canonicalize) whenever there are such vectors.
+// min0: the fewest span coordinates round 0's chunk may have (its register
+// slots can only be filled with spectator coordinates).
+void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<uint32_t> &lowspan,
+                     int min0, std::vector<uint32_t> *f, std::vector<int> *chunks) {
     std::vector<uint32_t> W, dg, rad;
     std::vector<std::pair<uint32_t, uint32_t>> pairs;
     for (int i = 0; i < rho; ++i) W.push_back(1u << i);
@@ -145,34 +152,70 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, std::vector<uint32
         odd = dg[0];
     }
     // even vectors: the partner, first vectors of the pairs, the radical,
-    // second vectors of the pairs; packed greedily into chunks of up to
-    // kRegBits mutually orthogonal vectors
+    // second vectors of the pairs
     std::vector<uint32_t> ev;
     if (partner) ev.push_back(partner);
     for (auto &pr : pairs) ev.push_back(pr.first);
     ev.insert(ev.end(), rad.begin(), rad.end());
     for (auto &pr : pairs) ev.push_back(pr.second);
+    // basis vectors that some low address bit depends on ("dirty")
+    std::vector<uint32_t> all(ev);
+    if (odd) all.push_back(odd);
+    std::vector<char> dirty(all.size(), 0);
+    {
+        std::vector<uint64_t> a64(all.begin(), all.end());
+        Coords ca(a64);
+        for (uint32_t v : lowspan) {
+            uint32_t co = 0;
+            if (!v || !ca.solve(v, &co)) continue;
+            for (size_t i = 0; i < all.size(); ++i)
+                if ((co >> i) & 1) dirty[i] = 1;
+        }
+    }
+    auto fits_in = [&](const std::vector<uint32_t> &c, uint32_t u) {
+        if ((int)c.size() >= kChunkBits) return false;
+        for (uint32_t w : c)
+            if (bil(B, u, w)) return false;
+        return true;
+    };
+    // Greedy packing into chunks of up to kChunkBits mutually orthogonal
+    // vectors: round 0's chunk first from clean even vectors (when a later
+    // chunk exists), then everything else in order.
+    auto pack = [&](bool clean_first, std::vector<std::vector<uint32_t>> *out) {
+        std::vector<std::vector<uint32_t>> &ch = *out;
+        ch.clear();
+        std::vector<uint32_t> rest;
+        if (clean_first) {
+            ch.push_back({});
+            for (size_t i = 0; i < ev.size(); ++i) {
+                if (!dirty[i] && fits_in(ch[0], ev[i])) ch[0].push_back(ev[i]);
+                else rest.push_back(ev[i]);
+            }
+            if (ch[0].empty()) ch.clear();
+        } else {
+            rest = ev;
+        }
+        const size_t first_open = ch.size();
+        for (uint32_t u : rest) {
+            if (ch.size() == first_open || !fits_in(ch.back(), u)) ch.push_back({});
+            ch.back().push_back(u);
+        }
+        // the odd vector opens the last chunk (the Lambda round): its S is
+        // the only i twiddle of the pass
+        if (odd) {
+            // (a dirty odd vector does not join a clean round-0 chunk)
+            const bool keep_clean = clean_first && ch.size() == 1 && dirty.back();
+            if (!ch.empty() && !keep_clean && fits_in(ch.back(), odd))
+                ch.back().insert(ch.back().begin(), odd);
+            else
+                ch.push_back({odd});
+        }
+    };
     std::vector<std::vector<uint32_t>> ch;
-    for (uint32_t u : ev) {
-        bool fits = !ch.empty() && (int)ch.back().size() < kRegBits;
-        if (fits)
-            for (uint32_t w : ch.back())
-                if (bil(B, u, w)) fits = false;
-        if (!fits) ch.push_back({});
-        ch.back().push_back(u);
-    }
-    // the odd vector opens the last chunk (the Lambda round): its S is the
-    // only i twiddle of the pass
-    if (odd) {
-        bool fits = !ch.empty() && (int)ch.back().size() < kRegBits;
-        if (fits)
-            for (uint32_t w : ch.back())
-                if (bil(B, odd, w)) fits = false;
-        if (fits)
-            ch.back().insert(ch.back().begin(), odd);
-        else
-            ch.push_back({odd});
-    }
+    bool any_dirty = false;
+    for (char d : dirty) any_dirty = any_dirty || d;
+    pack(any_dirty, &ch);
+    if (ch.size() > 4 || ch.empty() || (int)ch[0].size() < min0) pack(false, &ch);
     f->clear();
     chunks->clear();
     for (auto &c : ch) {
@@ -192,8 +235,63 @@ sd_status canonicalize(PassHost *ps) {
     p.chunk.clear();
     if (rho == 0) return SD_OK;
     std::vector<uint32_t> f;
-    canonical_basis(p.B, rho, &f, &p.chunk);
+    std::vector<uint32_t> lowspan;
+    const uint32_t rmk = (rho >= 32) ? ~0u : ((1u << rho) - 1);
+    for (int k = 0; k < p.c && k < 4 && k < (int)p.mr.size(); ++k) lowspan.push_back(p.mr[k] & rmk);
+    // round 0's register slots not taken by its chunk hold spectators
+    // (tiles below the register-round kernel's minimum run the generic kernel)
+    const bool rounds = p.D >= 2 * kRegBits + kXBits;
+    const int min0 = rounds ? std::min(rho, std::max(0, kRegBits - (p.D - rho))) : 0;
+    canonical_basis(p.B, rho, lowspan, min0, &f, &p.chunk);
+    if (!p.chunk.empty() && p.chunk[0] < min0)
+        return fail(SD_ERR_INTERNAL, "round 0 chunk too small for its register slots");
     if ((int)f.size() != rho) return fail(SD_ERR_INTERNAL, "canonical basis size");
+    // Round 0 moves the tile between HBM and registers directly, with its
+    // lanes running over the lowest address bits (coalescing).  A lane vector
+    // must have no component along the round's span coordinates (the
+    // butterflies would see shifted inputs), so the leading low bits' tile
+    // coordinates must lie in the span of the other chunks and the
+    // spectators.  The packing above builds chunk 0 that way when it can;
+    // among the chunks before the Lambda chunk, the one that leaves the
+    // longest run of such low bits goes first.
+    const int nch = (int)p.chunk.size();
+    if (nch >= 2) {
+        int best = 0, best_k = -1, off = 0;
+        std::vector<int> offs;
+        for (int r = 0; r < nch; ++r) {
+            offs.push_back(off);
+            off += p.chunk[r];
+        }
+        // the tile coordinates of address bit k in the new basis are
+        // M^-1 mr[k] on the span part; chunk r's part is its slice
+        std::vector<uint64_t> f64c(f.begin(), f.end());
+        Coords cfc(f64c);
+        const uint32_t rmc = (rho >= 32) ? ~0u : ((1u << rho) - 1);
+        for (int r = 0; r + 1 < nch; ++r) {
+            const uint32_t cm = ((1u << p.chunk[r]) - 1) << offs[r];
+            int k = 0;
+            while (k < p.c && k < (int)p.mr.size()) {
+                uint32_t yn = 0;
+                if (!cfc.solve(p.mr[k] & rmc, &yn) || (yn & cm)) break;
+                ++k;
+            }
+            if (k > best_k) {
+                best_k = k;
+                best = r;
+            }
+        }
+        if (best != 0) {
+            std::vector<uint32_t> g(f.begin() + offs[best], f.begin() + offs[best] + p.chunk[best]);
+            std::vector<int> sizes = {p.chunk[best]};
+            for (int r = 0; r < nch; ++r) {
+                if (r == best) continue;
+                g.insert(g.end(), f.begin() + offs[r], f.begin() + offs[r] + p.chunk[r]);
+                sizes.push_back(p.chunk[r]);
+            }
+            f = g;
+            p.chunk = sizes;
+        }
+    }
     std::vector<uint64_t> f64(f.begin(), f.end());
     Coords cf(f64);
     const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
@@ -235,64 +333,208 @@ sd_status canonicalize(PassHost *ps) {
 }
 
 // Register-round schedule for the on-chip transform of a tile with D
-// coordinates (span coordinates 0..rho-1, spectators rho..D-1).  A thread
-// holds 2^kRegBits amplitudes: the kRegBits tile coordinates of the current
-// round vary over them, the remaining coordinates are the thread index (lowest
-// first, so consecutive lanes touch consecutive on-chip slots).  Chunk r takes
-// the next chunk[r] span coordinates; a short chunk is filled with the highest
-// other coordinates, which are carried without butterflies.  Lambda is
-// applied in the round of the last chunk, between the two transforms.
+// coordinates (span coordinates 0..rho-1, spectators rho..D-1).
+//
+// A thread holds 2^kRegBits amplitudes.  Round r transforms chunk r (up to
+// kChunkBits span coordinates): its first kRegBits coordinates sit in the
+// register slots (their amplitudes of a thread differ in them); the next up
+// to kXBits sit on lane bits 4 and 5, and after the register butterflies they
+// are exchanged with register bits 2 and 3 (a lane permute inside the wave),
+// so their butterflies run in registers too.  The other coordinates are lane
+// bits.  A short chunk fills its register slots with other coordinates, which
+// are carried without butterflies; they are never span coordinates of a later
+// chunk (the CZs between a chunk and later chunks are applied as per-thread
+// sign patterns, which needs the later coordinates among the lane bits).
+// Lambda is applied in the round of the last chunk, between the two
+// transforms.
+//
+// Lane bits: in round 0, which moves the tile between HBM and registers
+// directly, lanes 0..c-1 are the tile coordinates of the c lowest address
+// bits (consecutive lanes then read consecutive amplitudes).  That needs
+// them free of components along the chunk's coordinates (the butterflies
+// would see shifted inputs) and independent of the registers; when they are
+// not, the pass is staged: the tile goes HBM -> LDS in pivot order (lanes over
+// the low pivots, as coalesced), and round 0 reads it from LDS.  Other lanes
+// are the lowest free unit coordinates.  Lanes 4 and 5 hold the
+// exchanged coordinates, the rest follow lowest first.
+//
+// The on-chip slot of tile coordinate t is t ^ sum_j parity(t & swz[j]) << j
+// (swz[j] only has bits >= 3, so the map is invertible); a 128-byte LDS
+// phase of 8 lanes is free of bank conflicts when the low three slot bits of
+// the round's three lowest lane vectors are independent.  The default masks
+// fold the 3-bit groups of t >> 3; when they fail some round, seeded random
+// masks are tried.
 sd_status plan_rounds(PassHost *ps) {
     PassHost &p = *ps;
     const int D = p.D, rho = p.rho;
+    const int RB = kRegBits, TL = D - RB;
     p.nr = 0;
     p.full_rounds = true;
-    for (int r = 0; r < 4; ++r) p.bmask[r] = p.iflag[r] = p.dflag[r] = p.later[r] = 0;
-    const int RB = kRegBits;
-    if (D < 2 * RB) {  // tiny tile: handled by the generic kernel only
+    for (int r = 0; r < 4; ++r) {
+        p.bmask[r] = p.iflag[r] = p.dflag[r] = p.later[r] = 0;
+        p.nx[r] = 0;
+        p.lanes[r].clear();
+        p.lanes_post[r].clear();
+    }
+    p.io_phys.clear();
+    p.io_k = 0;
+    p.staged = false;
+    if (D < 2 * RB + kXBits) {  // tiny tile: handled by the generic kernel only
         p.lam_round = 0;
-    } else {
-        auto fill = [&](int r, std::vector<int> bits, uint32_t bm) {
-            for (int b = D - 1; (int)bits.size() < RB && b >= 0; --b)
-                if (std::find(bits.begin(), bits.end(), b) == bits.end()) bits.push_back(b);
-            for (int i = 0; i < RB; ++i) p.reg[r][i] = (uint8_t)bits[i];
-            p.bmask[r] = bm;
-        };
-        if (rho == 0) {
-            fill(0, {}, 0u);
-            p.lam_round = 0;
-        } else {
-            p.nr = (int)p.chunk.size();
-            if (p.nr > 4) return fail(SD_ERR_INTERNAL, "too many register rounds");
-            int off = 0;
-            for (int r = 0; r < p.nr; ++r) {
-                std::vector<int> bits;
-                for (int b = off; b < off + p.chunk[r]; ++b) bits.push_back(b);
-                fill(r, bits, (1u << bits.size()) - 1);
-                for (int l = 0; l < p.chunk[r]; ++l) {
-                    const int a = off + l;
-                    if ((p.B[a] >> a) & 1) p.iflag[r] |= 1u << l;
-                    if ((p.zq >> a) & 1) p.dflag[r] |= 1u << l;
-                }
-                off += p.chunk[r];
-                for (int b = off; b < rho; ++b) p.later[r] |= 1u << b;
+        p.bucket.assign(33, 0);
+        p.bucket[1] = (int32_t)p.zeta.size();
+        for (int w = 1; w < 32; ++w) p.bucket[w + 1] = p.bucket[w];
+        p.coef_abs_sum = 0;
+        for (double c : p.coef) p.coef_abs_sum += std::fabs(c);
+        return SD_OK;
+    }
+    std::vector<int> chunks = p.chunk;
+    if (rho == 0) chunks = {0};
+    p.nr = rho == 0 ? 0 : (int)chunks.size();
+    const int nrounds = (int)chunks.size();
+    if (nrounds > 4) return fail(SD_ERR_INTERNAL, "too many register rounds");
+    int off = 0;
+    for (int r = 0; r < nrounds; ++r) {
+        const int s = chunks[r];
+        for (int b = off + s; b < rho; ++b) p.later[r] |= 1u << b;
+        std::vector<int> bits;
+        for (int b = off; b < off + std::min(s, RB); ++b) bits.push_back(b);
+        p.nx[r] = std::max(0, s - RB);
+        for (int x = 0; x < p.nx[r]; ++x) p.xl[r][x] = (uint8_t)(off + RB + x);
+        const uint32_t chunkm = s ? (((1u << s) - 1) << off) : 0u;
+        // fillers: highest coordinates outside the chunk and the later chunks;
+        // in round 0 first those that keep the low address bits independent
+        std::vector<int> cand;
+        for (int b = D - 1; b >= 0; --b)
+            if (!((chunkm >> b) & 1) && !((p.later[r] >> b) & 1)) cand.push_back(b);
+        if (r == 0) {
+            Echelon e;
+            for (int b = off; b < off + s; ++b) e.insert(1ull << b);
+            for (int k = 0; k < p.c && k < D; ++k)
+                if ((p.mr[k] & chunkm) || !e.insert(p.mr[k])) break;
+            for (int b : cand)
+                if ((int)bits.size() < RB && e.insert(1ull << b)) bits.push_back(b);
+        }
+        for (int b : cand)
+            if ((int)bits.size() < RB && std::find(bits.begin(), bits.end(), b) == bits.end())
+                bits.push_back(b);
+        if ((int)bits.size() < RB) return fail(SD_ERR_INTERNAL, "no filler coordinates left for a round");
+        for (int i = 0; i < RB; ++i) p.reg[r][i] = (uint8_t)bits[i];
+        p.bmask[r] = (1u << std::min(s, RB)) - 1;
+        for (int l = 0; l < RB; ++l) p.regpost[r][l] = p.reg[r][l];
+        for (int x = 0; x < p.nx[r]; ++x) p.regpost[r][2 + x] = p.xl[r][x];
+        for (int l = 0; l < s; ++l) {
+            const int a = off + l;
+            if ((p.B[a] >> a) & 1) p.iflag[r] |= 1u << l;
+            if ((p.zq >> a) & 1) p.dflag[r] |= 1u << l;
+        }
+        off += s;
+    }
+    p.lam_round = nrounds - 1;
+    for (int r = 0; r < p.lam_round; ++r)
+        if (chunks[r] != kChunkBits) p.full_rounds = false;
+    // the kernel twiddles only register slot 0 of the Lambda round
+    for (int r = 0; r < nrounds; ++r)
+        if (p.iflag[r] & ~(r == p.lam_round ? 1u : 0u))
+            return fail(SD_ERR_INTERNAL, "S outside slot 0 of the Lambda round");
+
+    // lane vectors
+    for (int r = 0; r < nrounds; ++r) {
+        Echelon e;
+        std::vector<uint32_t> ln(TL, 0u);
+        std::vector<char> set(TL, 0);
+        for (int l = 0; l < RB; ++l) e.insert(1ull << p.reg[r][l]);
+        for (int x = 0; x < p.nx[r]; ++x) {
+            e.insert(1ull << p.xl[r][x]);
+            ln[4 + x] = 1u << p.xl[r][x];
+            set[4 + x] = 1;
+        }
+        if (r == 0) {
+            // direct I/O needs all c leading low bits as clean lanes;
+            // otherwise the tile is staged through LDS in pivot order
+            const uint32_t chunkm = p.chunk.empty() ? 0u : (((1u << chunks[0]) - 1));
+            Echelon e2 = e;
+            int k = 0;
+            while (k < p.c && k < 4 && !(p.mr[k] & chunkm) && e2.insert(p.mr[k])) ++k;
+            p.staged = k < std::min(p.c, 4);
+            p.io_k = p.staged ? 0 : k;
+            for (int i = 0; i < p.io_k; ++i) {
+                e.insert(p.mr[i]);
+                ln[i] = p.mr[i];
+                set[i] = 1;
             }
-            p.lam_round = p.nr - 1;
-            p.full_rounds = true;
-            for (int r = 0; r < p.lam_round; ++r)
-                if (p.chunk[r] != RB) p.full_rounds = false;
-            // the kernel twiddles only register slot 0 of the Lambda round
-            for (int r = 0; r < p.nr; ++r)
-                if (p.iflag[r] & ~(r == p.lam_round ? 1u : 0u))
-                    return fail(SD_ERR_INTERNAL, "S outside slot 0 of the Lambda round");
+        }
+        int slot = 0;
+        for (int q = 0; q < D; ++q) {
+            while (slot < TL && set[slot]) ++slot;
+            if (slot >= TL) break;
+            if (e.insert(1ull << q)) {
+                ln[slot] = 1u << q;
+                set[slot] = 1;
+            }
+        }
+        for (int i = 0; i < TL; ++i)
+            if (!set[i]) return fail(SD_ERR_INTERNAL, "lane vectors do not span the tile");
+        p.lanes[r] = ln;
+        p.lanes_post[r] = ln;
+        for (int x = 0; x < p.nx[r]; ++x) p.lanes_post[r][4 + x] = 1u << p.reg[r][2 + x];
+    }
+    auto phys = [&](uint32_t v) {
+        uint64_t x = 0;
+        for (uint32_t w = v; w; w &= w - 1) x ^= p.basis[ctz(w)];
+        return x;
+    };
+    for (uint32_t t : p.lanes[0]) p.io_phys.push_back(phys(t));
+    for (int l = 0; l < RB; ++l) p.io_reg[l] = p.basis[p.reg[0][l]];
+    // lane triples whose LDS phases must be conflict free: every round, and
+    // the pivot-order staging of a staged pass
+    std::vector<std::array<uint32_t, 3>> triples;
+    for (int r = 0; r < nrounds; ++r) triples.push_back({p.lanes[r][0], p.lanes[r][1], p.lanes[r][2]});
+    if (p.staged) triples.push_back({p.mr[0], p.mr[1], p.mr[2]});
+    // swizzle masks: conflict-free 8-lane phases in every round
+    auto low3 = [](uint32_t v, const uint32_t *m) {
+        uint32_t g = v & 7u;
+        for (int j = 0; j < 3; ++j) g ^= (uint32_t)(popc(v & m[j]) & 1) << j;
+        return g;
+    };
+    auto score = [&](const uint32_t *m) {
+        int ok = 0;
+        for (auto &t : triples) {
+            const uint32_t a = low3(t[0], m), b = low3(t[1], m), c = low3(t[2], m);
+            if (a && b && c && (a ^ b) && (a ^ c) && (b ^ c) && (a ^ b ^ c)) ++ok;
+        }
+        return ok;
+    };
+    const uint32_t hi = (((1u << D) - 1) & ~7u);
+    uint32_t mk[3];
+    for (int j = 0; j < 3; ++j) {
+        mk[j] = 0;
+        for (int q = 3 + j; q < D; q += 3) mk[j] |= 1u << q;
+    }
+    int best = score(mk);
+    uint64_t rng = 0x9e3779b97f4a7c15ull ^ ((uint64_t)p.rho << 32) ^ (uint64_t)p.terms.size();
+    for (int it = 0; it < 4096 && best < (int)triples.size(); ++it) {
+        uint32_t cand[3];
+        for (int j = 0; j < 3; ++j) {
+            rng ^= rng << 13;
+            rng ^= rng >> 7;
+            rng ^= rng << 17;
+            cand[j] = (uint32_t)rng & hi;
+        }
+        const int sc = score(cand);
+        if (sc > best) {
+            best = sc;
+            for (int j = 0; j < 3; ++j) mk[j] = cand[j];
         }
     }
+    for (int j = 0; j < 3; ++j) p.swz[j] = mk[j];
+
     // sort the Lambda terms by their pattern on the Lambda round's registers
+    // (after the exchange)
     const int L = p.lam_round;
     auto pattern = [&](uint32_t z) {
         uint32_t w = 0;
-        if (D >= 2 * RB)
-            for (int i = 0; i < RB; ++i) w |= ((z >> p.reg[L][i]) & 1u) << i;
+        for (int i = 0; i < RB; ++i) w |= ((z >> p.regpost[L][i]) & 1u) << i;
         return w;
     };
     const size_t m = p.zeta.size();

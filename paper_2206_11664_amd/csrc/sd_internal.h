@@ -108,7 +108,9 @@ SynthResult synthesize(int n, const std::vector<Row> &terms, const SynthOptions 
 // ---------------------------------------------------------------------------
 constexpr int kMaxTileLog2 = 13;   // on-chip tile limit (LDS, FP64 staging)
 constexpr int kMinTileLog2 = 6;
-constexpr int kRegBits = 4;        // tile coordinates per register round
+constexpr int kRegBits = 4;        // tile coordinates held in registers per round
+constexpr int kXBits = 2;          // coordinates exchanged with lane bits 4, 5
+constexpr int kChunkBits = kRegBits + kXBits;   // span coordinates per round
 
 struct PassHost {
     int32_t group = -1;
@@ -127,15 +129,28 @@ struct PassHost {
     std::vector<double> coef;       // per term, c_k (-1)^{r_k} i^{e_k}
     double coef_abs_sum = 0;        // sum |c_k| (bounds the phase angle)
     // register-round schedule of the on-chip Walsh-Hadamard (see device.hip)
-    int nr = 0;                     // chunks of <= kRegBits span coordinates
+    int nr = 0;                     // chunks of <= kChunkBits span coordinates
     std::vector<int> chunk;         // span coordinates per chunk (contiguous)
-    uint8_t reg[4][8] = {};         // tile coordinates held in registers per chunk
+    uint8_t reg[4][8] = {};         // tile coordinates in register slots 0..3
+    uint8_t xl[4][2] = {};          // chunk coordinates on lane bits 4, 5
+    int nx[4] = {};                 // how many of them are exchanged with
+                                    // register bits 2, 3 (0..2)
+    uint8_t regpost[4][4] = {};     // register coordinates after the exchange
     uint32_t bmask[4] = {};         // register slots that get butterflies (low bits)
     uint32_t iflag[4] = {};         // register slots whose coordinate has an S
-    uint32_t dflag[4] = {};         // register slots whose coordinate has a Z
+    uint32_t dflag[4] = {};         // chunk slots (0..3 registers, 4..5 lanes) with a Z
     uint32_t later[4] = {};         // span coordinates of the chunks after r
     int lam_round = 0;              // chunk whose round applies Lambda
     bool full_rounds = true;        // every chunk before lam_round is full
+    // lane bit i of a thread is tile coordinate vector lanes[r][i] in round r
+    // before the exchange, lanes_post[r][i] after it; round 0 moves the tile
+    // between HBM and registers directly
+    std::vector<uint32_t> lanes[4], lanes_post[4];
+    std::vector<uint64_t> io_phys;  // physical offsets of round 0's lane vectors
+    uint64_t io_reg[4] = {};        // physical offsets of round 0's register slots
+    int io_k = 0;                   // leading lanes on the lowest address bits
+    bool staged = false;            // tile moves HBM <-> LDS in pivot order instead
+    uint32_t swz[3] = {};           // LDS swizzle: slot(t) = t ^ sum_j parity(t & swz[j]) << j
     std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
                                     // pattern on the registers of lam_round
 };

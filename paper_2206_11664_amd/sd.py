@@ -79,9 +79,15 @@ class sd_pass_view(ctypes.Structure):
 
 class sd_round_view(ctypes.Structure):
     _fields_ = [("n_rounds", ctypes.c_int32), ("lam_round", ctypes.c_int32),
-                ("reg", (ctypes.c_int32 * 4) * 4), ("bmask", ctypes.c_uint32 * 4),
-                ("iflag", ctypes.c_uint32 * 4), ("dflag", ctypes.c_uint32 * 4),
-                ("later", ctypes.c_uint32 * 4), ("bucket", ctypes.POINTER(ctypes.c_int32))]
+                ("reg", (ctypes.c_int32 * 4) * 4), ("regpost", (ctypes.c_int32 * 4) * 4),
+                ("xl", (ctypes.c_int32 * 2) * 4), ("nx", ctypes.c_int32 * 4),
+                ("bmask", ctypes.c_uint32 * 4), ("iflag", ctypes.c_uint32 * 4),
+                ("dflag", ctypes.c_uint32 * 4), ("later", ctypes.c_uint32 * 4),
+                ("bucket", ctypes.POINTER(ctypes.c_int32)),
+                ("n_lanes", ctypes.c_int32), ("io_coalesced", ctypes.c_int32),
+                ("lanes", ctypes.POINTER(ctypes.c_uint32) * 4),
+                ("lanes_post", ctypes.POINTER(ctypes.c_uint32) * 4),
+                ("swz", ctypes.c_uint32 * 3), ("staged", ctypes.c_int32)]
 
 
 _lib = None
@@ -281,10 +287,20 @@ def sd_plan_export_pass(p: int, dtype: int, i: int) -> dict:
 def sd_plan_export_rounds(p: int, dtype: int, i: int) -> dict:
     v = sd_round_view()
     _check(lib().sd_plan_export_rounds(p, dtype, i, ctypes.byref(v)))
+    nrounds = max(v.n_rounds, 1)
     return {"n_rounds": v.n_rounds, "lam_round": v.lam_round,
             "reg": [[v.reg[r][b] for b in range(4)] for r in range(4)],
-            "bmask": list(v.bmask), "iflag": list(v.iflag), "dflag": list(v.dflag),
-            "later": list(v.later), "bucket": [v.bucket[w] for w in range(17)]}
+            "regpost": [[v.regpost[r][b] for b in range(4)] for r in range(4)],
+            "xl": [[v.xl[r][x] for x in range(2)] for r in range(4)],
+            "nx": list(v.nx), "bmask": list(v.bmask), "iflag": list(v.iflag),
+            "dflag": list(v.dflag), "later": list(v.later),
+            "bucket": [v.bucket[w] for w in range(17)] if v.bucket else [0] * 17,
+            "io_coalesced": v.io_coalesced,
+            "lanes": [[v.lanes[r][i] for i in range(v.n_lanes)] if r < nrounds and v.n_lanes else []
+                      for r in range(4)],
+            "lanes_post": [[v.lanes_post[r][i] for i in range(v.n_lanes)]
+                           if r < nrounds and v.n_lanes else [] for r in range(4)],
+            "swz": list(v.swz), "staged": v.staged}
 
 
 def sd_plan_destroy(p: int):

@@ -4,6 +4,10 @@ It follows the GPU kernel's data movement step by step, vectorised over the
 threads of a block: each thread holds 16 amplitudes; in the round of chunk r
 they differ in the tile coordinates reg[r]; between rounds the tile goes
 through an on-chip array indexed by the swizzled slot of its tile coordinate.
+A round transforms up to 4 register coordinates, exchanges register bits 2,
+3 with lane bits 4, 5 (a lane permute inside the wave) and transforms the 2
+coordinates brought in.  Round 0 takes its amplitudes from the state vector
+directly and its inverse round writes them back directly.
 The CZ/S layer is not multiplied in: its S factors are i twiddles inside the
 butterflies, and its Z factors and cross-chunk CZ factors are XORs of the
 addresses a forward round writes to and the mirrored inverse round reads from
@@ -14,11 +18,12 @@ oracle.  Test code only; it is not the GPU path.
 import numpy as np
 
 
-def lds_slot(t):
+def lds_slot(t, swz):
     t = np.asarray(t, dtype=np.int64)
-    h = t >> 3
-    h = h ^ (h >> 3) ^ (h >> 6) ^ (h >> 9)
-    return t ^ (h & 7)
+    low = np.zeros(t.shape, dtype=np.int64)
+    for j in range(3):
+        low |= (_popc(t & swz[j]) & 1) << j
+    return t ^ low
 
 
 def _popc(v):
@@ -46,19 +51,42 @@ def _stage(R, L, tw, fwd):
             R[:, k] = np.conj(w) * (a - c)
 
 
-def _stages(R, nb, tw, fwd):
-    for L in range(nb):
-        _stage(R, L, (tw >> L) & 1, fwd)
+def _exchange(R, B, LB):
+    """Register bit B <-> lane bit LB: for each register pair (j, j | 2^B) a
+    2x2 transpose with the two lane halves (the lane permute of the kernel:
+    new x = x on lanes with bit LB clear, y of the partner lane otherwise;
+    new y = x of the partner lane where bit LB is clear, y otherwise)."""
+    T = R.shape[0]
+    t = np.arange(T)
+    hi = ((t >> LB) & 1).astype(bool)
+    partner = t ^ (1 << LB)
+    for j in range(16):
+        if (j >> B) & 1:
+            continue
+        k = j | (1 << B)
+        x, y = R[:, j].copy(), R[:, k].copy()
+        R[:, j] = np.where(hi, y[partner], x)
+        R[:, k] = np.where(hi, y, x[partner])
+
+
+def _xchg(R, nx):
+    if nx >= 1:
+        _exchange(R, 2, 4)
+    if nx == 2:
+        _exchange(R, 3, 5)
+
+
+def _stages_x(R, nx):
+    for L in range(2, 2 + nx):
+        _stage(R, L, 0, True)
 
 
 def apply_pass(psi, n, ps, rv, tau):
     """One tile pass: ps from sd_plan_export_pass, rv from sd_plan_export_rounds."""
-    D, rho, c = ps["tile_log2"], ps["rho"], ps["coalesce_log2"]
+    D, rho = ps["tile_log2"], ps["rho"]
     TL = D - 4
     T = 1 << TL
     tid = np.arange(T, dtype=np.int64)
-    pv = [int(v) for v in ps["pivot_vec"]]
-    mr = [int(v) for v in ps["pivot_coord"]]
     B = [int(v) for v in ps["cz_s"]]
     zeta = np.array([int(v) for v in ps["zeta"]], dtype=np.int64)
     ztile = [int(v) for v in ps["ztile"]]
@@ -66,73 +94,125 @@ def apply_pass(psi, n, ps, rv, tau):
     nr = rv["n_rounds"]
     nrounds = max(nr, 1)
     free = [q for q in range(n) if (ps["free_mask"] >> q) & 1]
-    # scatter/gather maps: element j of thread t is pivot pattern t + (j << TL)
-    off = np.zeros((T, 16), dtype=np.int64)
-    tc = np.zeros((T, 16), dtype=np.int64)
-    for j in range(16):
-        p = tid + (j << TL)
-        for i in range(D):
-            bit = (p >> i) & 1
-            off ^= 0  # keep shapes
-            off[:, j] ^= bit * pv[i]
-            tc[:, j] ^= bit * mr[i]
+    basis = [int(v) for v in ps["basis"]]
+    swz = rv["swz"]
+
+    def phys(y):
+        y = np.asarray(y, dtype=np.int64)
+        out = np.zeros(y.shape, dtype=np.int64)
+        for k in range(D):
+            out ^= ((y >> k) & 1) * basis[k]
+        return out
+
+    def base(vecs):
+        b = np.zeros(T, dtype=np.int64)
+        for i in range(TL):
+            b ^= ((tid >> i) & 1) * vecs[i]
+        return b
+
+    staged = bool(rv.get("staged", 0))
+    if staged:
+        # pivot order: element j of thread t is pivot pattern t + (j << TL)
+        pvv = [int(v) for v in ps["pivot_vec"]]
+        pcc = [int(v) for v in ps["pivot_coord"]]
+        soff = np.zeros((T, 16), dtype=np.int64)
+        stc = np.zeros((T, 16), dtype=np.int64)
+        for j in range(16):
+            pp = tid + (j << TL)
+            for i in range(D):
+                bit = (pp >> i) & 1
+                soff[:, j] ^= bit * pvv[i]
+                stc[:, j] ^= bit * pcc[i]
+        sslot = lds_slot(stc, swz)
+    # round 0: element g of thread t is tile coordinate bt0(t) ^ reg pattern g
+    bt0 = base(rv["lanes"][0])
+    y0 = np.zeros((T, 16), dtype=np.int64)
+    for g in range(16):
+        y0[:, g] = bt0
+        for b in range(4):
+            if (g >> b) & 1:
+                y0[:, g] ^= 1 << rv["reg"][0][b]
+    assert sorted(y0.ravel().tolist()) == list(range(1 << D))
+    off = phys(y0)
     # per-thread round addresses
     rd = np.zeros((nrounds, T), dtype=np.int64)
     wr = np.zeros((nrounds, T), dtype=np.int64)
     sgnb = None
     for r in range(nrounds):
-        regm = 0
-        for b in range(4):
-            regm |= 1 << rv["reg"][r][b]
-        bt = np.zeros(T, dtype=np.int64)
-        i = 0
-        for q in range(D):
-            if not (regm >> q) & 1:
-                bt |= ((tid >> i) & 1) << q
-                i += 1
+        bt = base(rv["lanes"][r])
+        btp = base(rv["lanes_post"][r])
         pm = np.zeros(T, dtype=np.int64)
-        for l in range(4):
-            if (rv["bmask"][r] >> l) & 1:
+        for l in range(6):
+            if l < 4:
+                if not (rv["bmask"][r] >> l) & 1:
+                    continue
                 a = rv["reg"][r][l]
-                bit = (_popc(B[a] & rv["later"][r] & bt) ^ (rv["dflag"][r] >> l)) & 1
-                pm |= bit << a
-        rd[r] = lds_slot(bt)
+            elif l - 4 < rv["nx"][r]:
+                a = rv["xl"][r][l - 4]
+            else:
+                continue
+            bit = (_popc(B[a] & rv["later"][r] & bt) ^ (rv["dflag"][r] >> l)) & 1
+            pm |= bit << a
+        rd[r] = lds_slot(bt, swz)
         if r == nrounds - 1:
-            sgnb = bt ^ pm
+            sgnb = btp ^ pm
             wr[r] = rd[r]
         else:
-            wr[r] = lds_slot(bt ^ pm)
-    rs = [[int(lds_slot(1 << rv["reg"][r][b])) for b in range(4)] for r in range(4)]
+            wr[r] = lds_slot(btp ^ pm, swz)
+    rs_pre = [[int(lds_slot(1 << rv["reg"][r][b], swz)) for b in range(4)] for r in range(4)]
+    rs_post = [[int(lds_slot(1 << rv["regpost"][r][b], swz)) for b in range(4)] for r in range(4)]
     bucket = rv["bucket"]
     scale = 2.0 ** (-rho)
     out = np.array(psi, dtype=np.complex128, copy=True)
     lds = np.zeros(1 << D, dtype=np.complex128)
+
+    def addr(start, offs):
+        a = np.zeros((T, 16), dtype=np.int64)
+        for g in range(16):
+            a[:, g] = start
+            for b in range(4):
+                if (g >> b) & 1:
+                    a[:, g] ^= offs[b]
+        return a
+
     for ti in range(1 << (n - D)):
         xT = 0
         for i, q in enumerate(free):
             if (ti >> i) & 1:
                 xT |= 1 << q
-        lds[lds_slot(tc)] = out[xT ^ off]
         cks = np.array([(-1.0 if bin(zt & xT).count("1") & 1 else 1.0) * cf
                         for zt, cf in zip(ztile, coef)])
         total = 2 * nr - 1 if nr > 0 else 1
+        if staged:
+            lds[sslot] = out[xT ^ soff]
         for step in range(total):
             r = step if step < nrounds else 2 * nr - 2 - step
             lam = step == nrounds - 1
             fwd = step < nrounds - 1
+            last = step == total - 1
             ra = rd[r] if (fwd or lam) else wr[r]
             wa = wr[r] if fwd else rd[r]
-            R = np.zeros((T, 16), dtype=np.complex128)
-            for g in range(16):
-                a = ra.copy()
-                for b in range(4):
-                    if (g >> b) & 1:
-                        a ^= rs[r][b]
-                R[:, g] = lds[a]
+            rin = rs_pre[r] if (fwd or lam) else rs_post[r]
+            rout = rs_post[r] if fwd else rs_pre[r]
+            if step == 0 and not staged:
+                R = out[xT ^ off].astype(np.complex128)
+            else:
+                R = lds[addr(ra, rin)]
             nb = bin(rv["bmask"][r]).count("1")
-            tw = rv["iflag"][r]
-            if lam:
-                _stages(R, nb, tw, True)
+            nx = rv["nx"][r]
+            tw = rv["iflag"][r] & 1
+            if not lam:
+                for L in range(nb):
+                    _stage(R, L, 0, True)
+                _xchg(R, nx)
+                _stages_x(R, nx)
+            else:
+                if nb:
+                    _stage(R, 0, tw, True)
+                    for L in range(1, nb):
+                        _stage(R, L, 0, True)
+                    _xchg(R, nx)
+                    _stages_x(R, nx)
                 S = np.zeros((T, 16))
                 for w in range(16):
                     for k in range(bucket[w], bucket[w + 1]):
@@ -145,18 +225,18 @@ def apply_pass(psi, n, ps, rv, tau):
                             a0, a1 = A[:, j].copy(), A[:, j | (1 << b)].copy()
                             A[:, j], A[:, j | (1 << b)] = a0 + a1, a0 - a1
                 R = R * np.exp(-1j * tau * A) * scale
-                _stages(R, nb, tw, False)
-            elif fwd:
-                _stages(R, nb, tw, True)
+                if nb:
+                    _stages_x(R, nx)
+                    _xchg(R, nx)
+                    for L in range(1, nb):
+                        _stage(R, L, 0, False)
+                    _stage(R, 0, tw, False)
+            if last and not staged:
+                out[xT ^ off] = R
             else:
-                _stages(R, nb, tw, False)
-            for g in range(16):
-                a = wa.copy()
-                for b in range(4):
-                    if (g >> b) & 1:
-                        a ^= rs[r][b]
-                lds[a] = R[:, g]
-        out[xT ^ off] = lds[lds_slot(tc)]
+                lds[addr(wa, rout)] = R
+        if staged:
+            out[xT ^ soff] = lds[sslot]
     return out
 
 

@@ -323,9 +323,12 @@ def _export_all(p, dtype):
 
 
 def _check_round_structure(ps, rv):
-    """Chunks hold consecutive span coordinates and no CZ inside a chunk; the
-    only S sits in register slot 0 of the Lambda round."""
+    """Chunks hold consecutive span coordinates (register slots first, then
+    the exchanged lane coordinates) and no CZ inside a chunk; fillers are never
+    span coordinates of a later chunk; the only S sits in register slot 0 of
+    the Lambda round; round 0's leading lanes are the lowest address bits."""
     rho, B = ps["rho"], [int(v) for v in ps["cz_s"]]
+    D = ps["tile_log2"]
     nr = rv["n_rounds"]
     if rho == 0:
         assert nr == 0
@@ -333,21 +336,47 @@ def _check_round_structure(ps, rv):
     seen = []
     for r in range(nr):
         nb = bin(rv["bmask"][r]).count("1")
-        assert rv["bmask"][r] == (1 << nb) - 1 and 1 <= nb <= 4
-        coords = [rv["reg"][r][l] for l in range(nb)]
-        assert coords == list(range(len(seen), len(seen) + nb))
+        nx = rv["nx"][r]
+        assert rv["bmask"][r] == (1 << nb) - 1 and 1 <= nb <= 4 and 0 <= nx <= 2
+        assert nx == 0 or nb == 4
+        coords = [rv["reg"][r][l] for l in range(nb)] + [rv["xl"][r][x] for x in range(nx)]
+        assert coords == list(range(len(seen), len(seen) + nb + nx))
         seen += coords
         cm = sum(1 << a for a in coords)
         for l, a in enumerate(coords):
             assert B[a] & cm & ~(1 << a) == 0, "CZ inside a register chunk"
             assert ((rv["iflag"][r] >> l) & 1) == ((B[a] >> a) & 1)
+            assert ((rv["dflag"][r] >> l) & 1) == ((ps["z_sign"] >> a) & 1)
             if (B[a] >> a) & 1:
                 assert r == nr - 1 and l == 0
-            assert ((rv["dflag"][r] >> l) & 1) == ((ps["z_sign"] >> a) & 1)
         assert rv["later"][r] == sum(1 << b for b in range(len(seen), rho))
+        for l in range(nb, 4):
+            assert not (rv["later"][r] >> rv["reg"][r][l]) & 1
+        post = list(rv["reg"][r])
+        for x in range(nx):
+            post[2 + x] = rv["xl"][r][x]
+        assert rv["regpost"][r] == post
+        # lane vectors: with the register slots they span the tile
+        vecs = [1 << q for q in rv["reg"][r]] + list(rv["lanes"][r])
+        assert _rank(vecs) == D
+        assert rv["lanes"][r][4:4 + nx] == [1 << rv["xl"][r][x] for x in range(nx)]
     assert seen == list(range(rho)) and rv["lam_round"] == nr - 1
     bk = rv["bucket"]
     assert bk[0] == 0 and bk[16] == len(ps["coef"]) and all(bk[w] <= bk[w + 1] for w in range(16))
+    k = rv["io_coalesced"]
+    assert rv["lanes"][0][:k] == [int(v) for v in ps["pivot_coord"][:k]]
+    c = min(ps["coalesce_log2"], 4)
+    assert (k == c) != bool(rv["staged"])
+
+
+def _rank(vs):
+    basis = []
+    for v in vs:
+        for b in basis:
+            v = min(v, v ^ b)
+        if v:
+            basis.append(v)
+    return len(basis)
 
 
 @pytest.mark.parametrize("seed,rho,alt", [(1, 9, False), (2, 9, True), (3, 8, True), (4, 6, True),
@@ -377,7 +406,7 @@ def test_register_rounds_large_group_matches_oracle(seed, rho, alt):
     assert np.abs(got - want).max() < 1e-13
 
 
-@pytest.mark.parametrize("case", ["klocal", "xxz", "jw", "wide"])
+@pytest.mark.parametrize("case", ["klocal", "xxz", "jw", "wide", "n16"])
 @pytest.mark.parametrize("dtype", [sd.SD_C64, sd.SD_C128])
 def test_register_rounds_models_match_oracle(case, dtype):
     if case == "klocal":
@@ -386,8 +415,10 @@ def test_register_rounds_models_match_oracle(case, dtype):
         m, D = workloads.xxz_chain(n=11, steps=3), 10
     elif case == "jw":
         m, D = workloads.jw_fermionic(n=11, total=150), 10
-    else:
+    elif case == "wide":
         m, D = workloads.random_klocal(n=15, m=300, seed=11, init_seed=2), 13
+    else:
+        m, D = workloads.random_klocal(n=16, m=400, seed=3, init_seed=30), 13
     h, p = plan_for(m.n, m.paulis, m.coeffs, tile_log2_c64=D, tile_log2_c128=D)
     info = sd.sd_plan_info_get(p)
     passes, rounds = _export_all(p, dtype)
@@ -397,3 +428,17 @@ def test_register_rounds_models_match_oracle(case, dtype):
     got = round_emulator.evolve(psi0, m.n, passes, rounds, info.n_groups, 0.11, 1, 2)
     want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.11, 1, 2)
     assert np.abs(got - want).max() < 1e-13
+
+
+@pytest.mark.parametrize("which", ["klocal28", "jw32", "xxz26"])
+def test_register_round_structure_full_size(which):
+    # every pass of the benchmark-size plans satisfies the round invariants
+    m = {"klocal28": lambda: workloads.random_klocal(n=28),
+         "jw32": lambda: workloads.jw_fermionic(n=32),
+         "xxz26": lambda: workloads.xxz_chain(n=26)}[which]()
+    h, p = plan_for(m.n, m.paulis, m.coeffs)
+    for dtype in (sd.SD_C64, sd.SD_C128):
+        passes, rounds = _export_all(p, dtype)
+        for q, r in zip(passes, rounds):
+            if q["tile_log2"] >= 10:
+                _check_round_structure(q, r)
