@@ -232,7 +232,7 @@ typedef struct {
     int32_t io_coalesced;
     const uint32_t *lanes[4];
     const uint32_t *lanes_post[4];
-    uint32_t swz[3];
+    uint32_t swz[4];
     int32_t staged;            /* 1: the tile moves between HBM and LDS in pivot
                                   order (pivot_vec / pivot_coord of the pass
                                   view) and round 0 reads it from LDS; used when

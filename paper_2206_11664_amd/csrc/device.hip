@@ -79,7 +79,7 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         d.coef_abs_sum = p.coef_abs_sum;
         for (size_t i = 0; i < p.io_phys.size() && i < (size_t)kMaxD; ++i) d.io_phys[i] = p.io_phys[i];
         for (int l = 0; l < 4; ++l) d.io_reg[l] = p.io_reg[l];
-        for (int j = 0; j < 3; ++j) d.swz[j] = p.swz[j];
+        for (int j = 0; j < 4; ++j) d.swz[j] = p.swz[j];
         d.staged = p.staged ? 1 : 0;
         std::memcpy(buf.data() + i * sizeof(PassDev), &d, sizeof(d));
         uint8_t *t = buf.data() + toff;
@@ -252,8 +252,9 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
 // the others (taken from the thread index), so the butterflies of those
 // coordinates run in registers; between rounds the tile is exchanged through
 // LDS.  The LDS slot of tile coordinate t is t ^ sum_j parity(t & swz[j]) << j
-// with per-pass masks that the planner picks so that, in every round, the 8
-// lanes of a 128-byte LDS phase hit distinct banks.  The slot map is linear
+// with per-pass masks that the planner picks so that, in every round, the
+// lanes served together hit distinct banks: 8 lanes per 128-byte phase for
+// 16-byte writes, 16 lanes per 256-byte phase for 16-byte reads on gfx950.  The slot map is linear
 // over GF(2), so every address is a per-thread base XOR a uniform offset; the
 // tile sits at LDS address 0 and addresses are plain byte offsets (no static
 // LDS in these kernels).
@@ -474,10 +475,10 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
         const double th = fabs(tau) * pd.coef_abs_sum;
         while (halv < 60 && ldexp(th, -halv) > 0.25) ++halv;
     }
-    const uint32_t sw0 = pd.swz[0], sw1 = pd.swz[1], sw2 = pd.swz[2];
+    const uint32_t sw0 = pd.swz[0], sw1 = pd.swz[1], sw2 = pd.swz[2], sw3 = pd.swz[3];
     auto slot = [&](uint32_t t) {
         return t ^ ((uint32_t)(__popc(t & sw0) & 1) | ((uint32_t)(__popc(t & sw1) & 1) << 1) |
-                    ((uint32_t)(__popc(t & sw2) & 1) << 2));
+                    ((uint32_t)(__popc(t & sw2) & 1) << 2) | ((uint32_t)(__popc(t & sw3) & 1) << 3));
     };
     if (tid < 4 * kLE) {
         s_rs[tid] = slot(1u << pd.reg[tid / kLE][tid % kLE]) * 16u;
@@ -714,11 +715,10 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     // ones; backward (from the layout after it) the same sequence transforms
     // the exchanged coordinates first.  Butterflies on different coordinates
     // commute and carry no twiddle outside the Lambda round, so both
-    // directions are the same code.  Step 0 takes its input from pre[] (or
-    // from re/im loaded before) and, with PF, then refills pre[] with the next
-    // tile's round-0 amplitudes; the last step stores to HBM.  Every step ends
-    // with a block barrier.
-    auto transform = [&](OFF xb, bool pf_next, OFF xb_next) {
+    // directions are the same code.  Step 0 of a direct pass finds its input
+    // in re/im already and its last step leaves the results there.  Every
+    // step ends with a block barrier.
+    auto transform = [&](OFF xb) {
         const int total = nr > 0 ? 2 * nr - 1 : 1;
         for (int step = 0; step < total; ++step) {
             const int r = step < nrounds ? step : 2 * nr - 2 - step;
@@ -738,14 +738,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             }
             const int nb = __popc(pd.bmask[r]);
             const int nx = pd.nx[r];
-            if (step == 0 && !staged) {
-                if (PF) {
-                    from_pre();
-                    if (pf_next) load_tile(xb_next);
-                }
-            } else {
-                read16(ra, rin);
-            }
+            if (step > 0 || staged) read16(ra, rin);  // (step 0 of a direct pass: in re/im)
             if (!lam) {
                 bfly_fwd<0, false>(re, im);
                 if (GEN) {
@@ -761,8 +754,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                     bfly_fwd<2, false>(re, im);
                     bfly_fwd<3, false>(re, im);
                 }
-                if (last && !staged) store16(xb);
-                else write16(wa, rout);
+                if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
                 __syncthreads();
                 continue;
             }
@@ -838,10 +830,12 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                 if (tw) bfly_bwd<0, true>(re, im);
                 else bfly_bwd<0, false>(re, im);
             }
-            if (last && !staged) store16(xb);
-            else write16(wa, rout);
+            if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
             __syncthreads();
         }
+        // a direct pass's results: stored here without the prefetch, else at
+        // the top of the next tile (see below)
+        if (MODE == 0 && !staged && !PF) store16(xb);
     };
 
     __syncthreads();
@@ -851,24 +845,37 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
         // tile t; the stores of tile t are issued after them (one counter
         // tracks loads and stores in issue order, so waiting for the next
         // tile's loads does not wait for these stores).
-        // A staged pass scatters pre[] to LDS first and issues the next
-        // loads right after that.
+        // pre[] is converted into re/im (or, staged, scattered to LDS) before
+        // the rounds start, and the next tile's loads go into it right away;
+        // keeping that outside the round loop keeps pre[] one plain live range.
+        // The results of a direct pass stay in re/im until the top of the next
+        // tile and are stored right before its prefetched amplitudes are
+        // consumed: one counter tracks loads and stores in issue order, and
+        // these stores are younger than the loads waited for, so that wait
+        // does not include them (in straight-line code the compiler counts
+        // them exactly).
         if (t0 < t1) load_tile(tile_off(t0));
+        bool have_prev = false;
+        OFF xb_prev = 0;
         for (int64_t ti = t0; ti < t1; ti += stride) {
             const OFF xb = tile_off(ti);
             const int64_t tn = ti + stride;
+            if (have_prev) store16(xb_prev);
+            if (staged) scatter_pre();
+            else from_pre();
+            if (tn < t1) load_tile(tile_off(tn));
             signs(xb);
-            if (staged) {
-                scatter_pre();
-                if (tn < t1) load_tile(tile_off(tn));
-            }
             __syncthreads();
-            transform(xb, tn < t1, tn < t1 ? tile_off(tn) : (OFF)0);
+            transform(xb);
             if (staged) {
                 if (MODE == 0) gather(xb);
                 __syncthreads();
+            } else {
+                have_prev = true;
+                xb_prev = xb;
             }
         }
+        if (have_prev) store16(xb_prev);
     } else {
         for (int64_t ti = t0; ti < t1; ti += stride) {
             const OFF xb = tile_off(ti);
@@ -876,7 +883,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             signs(xb);
             if (staged) scatter_regs();
             __syncthreads();
-            transform(xb, false, (OFF)0);
+            transform(xb);
             if (staged) {
                 if (MODE == 0) gather(xb);
                 __syncthreads();

@@ -40,7 +40,7 @@ struct alignas(256) PassDev {
     uint32_t lanes_post[4][kMaxD];  // the same after the lane exchange
     uint64_t io_phys[kMaxD];        // physical offsets of round 0's lane bits
     uint64_t io_reg[4];             // physical offsets of round 0's register slots
-    uint32_t swz[3];                // LDS slot of t: t ^ sum_j parity(t & swz[j]) << j
+    uint32_t swz[4];                // LDS slot of t: t ^ sum_j parity(t & swz[j]) << j
     int32_t staged;                 // round 0 reads the tile from LDS, staged in
                                     // pivot order (u_hi, mr), not from HBM
 };

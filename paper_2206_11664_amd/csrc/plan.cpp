@@ -219,7 +219,7 @@ extern "C" sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int3
     v->bucket = h.bucket.data();
     v->n_lanes = (int32_t)h.lanes[0].size();
     v->io_coalesced = h.io_k;
-    for (int j = 0; j < 3; ++j) v->swz[j] = h.swz[j];
+    for (int j = 0; j < 4; ++j) v->swz[j] = h.swz[j];
     v->staged = h.staged ? 1 : 0;
     return SD_OK;
 }

@@ -359,11 +359,14 @@ sd_status canonicalize(PassHost *ps) {
 // exchanged coordinates, the rest follow lowest first.
 //
 // The on-chip slot of tile coordinate t is t ^ sum_j parity(t & swz[j]) << j
-// (swz[j] only has bits >= 3, so the map is invertible); a 128-byte LDS
-// phase of 8 lanes is free of bank conflicts when the low three slot bits of
-// the round's three lowest lane vectors are independent.  The default masks
-// fold the 3-bit groups of t >> 3; when they fail some round, seeded random
-// masks are tried.
+// for j = 0..3 (swz[0..2] only have bits >= 3 and swz[3] bits >= 4, so the
+// map is invertible).  On
+// gfx950 a 16-byte LDS write serves 8 lanes per 128-byte phase and a 16-byte
+// read 16 lanes per 256-byte phase, so a layout is free of bank conflicts
+// when the low 3 slot bits of lane vectors 0..2 and the low 4 slot bits of
+// lane vectors 0..3 are independent.  The default masks fold the 4-bit
+// groups of t >> 4; when they fail some layout, seeded random masks are
+// tried.
 sd_status plan_rounds(PassHost *ps) {
     PassHost &p = *ps;
     const int D = p.D, rho = p.rho;
@@ -486,48 +489,61 @@ sd_status plan_rounds(PassHost *ps) {
     };
     for (uint32_t t : p.lanes[0]) p.io_phys.push_back(phys(t));
     for (int l = 0; l < RB; ++l) p.io_reg[l] = p.basis[p.reg[0][l]];
-    // lane triples whose LDS phases must be conflict free: every round, and
-    // the pivot-order staging of a staged pass
-    std::vector<std::array<uint32_t, 3>> triples;
-    for (int r = 0; r < nrounds; ++r) triples.push_back({p.lanes[r][0], p.lanes[r][1], p.lanes[r][2]});
-    if (p.staged) triples.push_back({p.mr[0], p.mr[1], p.mr[2]});
-    // swizzle masks: conflict-free 8-lane phases in every round
-    auto low3 = [](uint32_t v, const uint32_t *m) {
-        uint32_t g = v & 7u;
-        for (int j = 0; j < 3; ++j) g ^= (uint32_t)(popc(v & m[j]) & 1) << j;
+    // Lane vectors of every LDS layout (every round, and the pivot-order
+    // staging of a staged pass).  16-byte writes serve 8 lanes (bits 0..2)
+    // per 128-byte phase, 16-byte reads 16 lanes (bits 0..3) per 256-byte
+    // phase: the low 3 slot bits of lanes 0..2 and the low 4 slot bits of
+    // lanes 0..3 must be independent.
+    std::vector<std::array<uint32_t, 4>> quads;
+    for (int r = 0; r < nrounds; ++r)
+        quads.push_back({p.lanes[r][0], p.lanes[r][1], p.lanes[r][2], p.lanes[r][3]});
+    if (p.staged) quads.push_back({p.mr[0], p.mr[1], p.mr[2], p.mr[3]});
+    auto lowbits = [](uint32_t v, const uint32_t *m, int nb) {
+        uint32_t g = v & ((1u << nb) - 1);
+        for (int j = 0; j < nb; ++j) g ^= (uint32_t)(popc(v & m[j]) & 1) << j;
         return g;
+    };
+    auto indep = [](std::vector<uint32_t> v) {
+        Echelon e;
+        for (uint32_t x : v)
+            if (!e.insert(x)) return false;
+        return true;
     };
     auto score = [&](const uint32_t *m) {
         int ok = 0;
-        for (auto &t : triples) {
-            const uint32_t a = low3(t[0], m), b = low3(t[1], m), c = low3(t[2], m);
-            if (a && b && c && (a ^ b) && (a ^ c) && (b ^ c) && (a ^ b ^ c)) ++ok;
+        for (auto &q : quads) {
+            if (indep({lowbits(q[0], m, 3), lowbits(q[1], m, 3), lowbits(q[2], m, 3)})) ++ok;
+            if (indep({lowbits(q[0], m, 4), lowbits(q[1], m, 4), lowbits(q[2], m, 4), lowbits(q[3], m, 4)})) ++ok;
         }
         return ok;
     };
-    const uint32_t hi = (((1u << D) - 1) & ~7u);
-    uint32_t mk[3];
-    for (int j = 0; j < 3; ++j) {
+    const int target = 2 * (int)quads.size();
+    // slot bit j < 3 may fold in bits >= 3, slot bit 3 bits >= 4: the map
+    // stays triangular, hence invertible
+    const uint32_t all = (1u << D) - 1;
+    const uint32_t hm[4] = {all & ~7u, all & ~7u, all & ~7u, all & ~15u};
+    uint32_t mk[4];
+    for (int j = 0; j < 4; ++j) {
         mk[j] = 0;
-        for (int q = 3 + j; q < D; q += 3) mk[j] |= 1u << q;
+        for (int q = 4 + j; q < D; q += 4) mk[j] |= 1u << q;
     }
     int best = score(mk);
     uint64_t rng = 0x9e3779b97f4a7c15ull ^ ((uint64_t)p.rho << 32) ^ (uint64_t)p.terms.size();
-    for (int it = 0; it < 4096 && best < (int)triples.size(); ++it) {
-        uint32_t cand[3];
-        for (int j = 0; j < 3; ++j) {
+    for (int it = 0; it < 8192 && best < target; ++it) {
+        uint32_t cand[4];
+        for (int j = 0; j < 4; ++j) {
             rng ^= rng << 13;
             rng ^= rng >> 7;
             rng ^= rng << 17;
-            cand[j] = (uint32_t)rng & hi;
+            cand[j] = (uint32_t)rng & hm[j];
         }
         const int sc = score(cand);
         if (sc > best) {
             best = sc;
-            for (int j = 0; j < 3; ++j) mk[j] = cand[j];
+            for (int j = 0; j < 4; ++j) mk[j] = cand[j];
         }
     }
-    for (int j = 0; j < 3; ++j) p.swz[j] = mk[j];
+    for (int j = 0; j < 4; ++j) p.swz[j] = mk[j];
 
     // sort the Lambda terms by their pattern on the Lambda round's registers
     // (after the exchange)

@@ -150,7 +150,7 @@ struct PassHost {
     uint64_t io_reg[4] = {};        // physical offsets of round 0's register slots
     int io_k = 0;                   // leading lanes on the lowest address bits
     bool staged = false;            // tile moves HBM <-> LDS in pivot order instead
-    uint32_t swz[3] = {};           // LDS swizzle: slot(t) = t ^ sum_j parity(t & swz[j]) << j
+    uint32_t swz[4] = {};           // LDS swizzle: slot(t) = t ^ sum_j parity(t & swz[j]) << j
     std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
                                     // pattern on the registers of lam_round
 };

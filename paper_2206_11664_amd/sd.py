@@ -87,7 +87,7 @@ class sd_round_view(ctypes.Structure):
                 ("n_lanes", ctypes.c_int32), ("io_coalesced", ctypes.c_int32),
                 ("lanes", ctypes.POINTER(ctypes.c_uint32) * 4),
                 ("lanes_post", ctypes.POINTER(ctypes.c_uint32) * 4),
-                ("swz", ctypes.c_uint32 * 3), ("staged", ctypes.c_int32)]
+                ("swz", ctypes.c_uint32 * 4), ("staged", ctypes.c_int32)]
 
 
 _lib = None

@@ -21,7 +21,7 @@ import numpy as np
 def lds_slot(t, swz):
     t = np.asarray(t, dtype=np.int64)
     low = np.zeros(t.shape, dtype=np.int64)
-    for j in range(3):
+    for j in range(len(swz)):
         low |= (_popc(t & swz[j]) & 1) << j
     return t ^ low
 
