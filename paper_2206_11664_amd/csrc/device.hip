@@ -371,6 +371,25 @@ __device__ __forceinline__ void bfly_fwd(double (&re)[kE], double (&im)[kE]) {
         }
 }
 
+// The same plain butterfly computed in place: the sum overwrites a, then
+// the difference is the sum minus 2c (one FMA), so each result can take the
+// register of the input it replaces.  Used where a stage runs under a branch:
+// there the usual form leaves the sums in new registers that the join then
+// moves back.  Its difference is rounded from the rounded sum, an error of
+// the same size as the sum's own.
+template <int L>
+__device__ __forceinline__ void bfly_ip(double (&re)[kE], double (&im)[kE]) {
+#pragma unroll
+    for (int j = 0; j < kE; ++j)
+        if (!((j >> L) & 1)) {
+            const int k = j | (1 << L);
+            re[j] = re[j] + re[k];
+            im[j] = im[j] + im[k];
+            re[k] = fma(-2.0, re[k], re[j]);
+            im[k] = fma(-2.0, im[k], im[j]);
+        }
+}
+
 template <int L, bool TW>
 __device__ __forceinline__ void bfly_bwd(double (&re)[kE], double (&im)[kE]) {
 #pragma unroll
@@ -454,7 +473,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     constexpr bool FULL = sizeof(T) == 16;
     // complex128 tiles and the general round code skip the register
     // prefetch of the next tile: it would not fit two waves per SIMD
-    constexpr bool PF = MODE == 0 && sizeof(T) == 8 && !GEN;
+    constexpr bool PF = MODE == 0 && sizeof(T) == 8;
     extern __shared__ double2 lds_dyn[];
     const PassDev &pd = *pdp;
     const int D = pd.D, TL = D - kLE, m = pd.m, nr = pd.nr;
@@ -676,22 +695,9 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     };
     // plain butterflies on register bits 1..nb-1 (they commute)
     auto plain_rest = [&](int nb) {
-        switch (nb) {
-            case 4:
-                bfly_fwd<1, false>(re, im);
-                bfly_fwd<2, false>(re, im);
-                bfly_fwd<3, false>(re, im);
-                break;
-            case 3:
-                bfly_fwd<1, false>(re, im);
-                bfly_fwd<2, false>(re, im);
-                break;
-            case 2:
-                bfly_fwd<1, false>(re, im);
-                break;
-            default:
-                break;
-        }
+        if (nb > 1) bfly_ip<1>(re, im);
+        if (nb > 2) bfly_ip<2>(re, im);
+        if (nb > 3) bfly_ip<3>(re, im);
     };
 
     // The rounds of one tile.  Step 0 takes its input from pre[] and, with
@@ -704,8 +710,8 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
         if (nx == 2) exch<3, 5>(re, im);
     };
     auto stages_x = [&](int nx) {
-        if (nx >= 1) bfly_fwd<2, false>(re, im);
-        if (nx == 2) bfly_fwd<3, false>(re, im);
+        if (nx >= 1) bfly_ip<2>(re, im);
+        if (nx == 2) bfly_ip<3>(re, im);
     };
 
     // The rounds of one tile.  A round other than Lambda's runs butterflies
