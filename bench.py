@@ -11,6 +11,7 @@ the fidelity figure.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +22,42 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+ROOFLINE_KERNEL = "sd::k_tile<float2, 0, uint32_t, GEN>"   # both GEN instantiations
+COUNTERS = os.path.join(ROOT, "profiles", "k_tile_c64_n28_hbm_counters.txt")
+
+
+def kernel_source_digest():
+    """sha256 over the library's sources: the traffic figure in the counter
+    summary is valid only for the sources it was measured with."""
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2206_11664_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per k_tile launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's
+    reading for a plain copy of known size), or None when the summary is
+    missing or was taken with other kernel sources."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -36,6 +73,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=16)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain elementwise copy (negation) of a 2^n complex64 "
+                         "vector, the calibration kernel of the HBM counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -108,10 +148,20 @@ def main():
     e0 = plan.expectation(d128_0)
     del diff, b64, b128, a64, a128
 
+    if args.calib_copy:
+        log("calibration copy")
+        src = torch.ones(dim, dtype=torch.complex64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {dim * 8} bytes read, {dim * 8} bytes written")
+        del src, dst
+
     launches = args.steps * info.passes_c64
     avg_launch_s = t64 / launches
     bytes_per_launch = 2 * dim * 8
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = counter_traffic()
     result = {
         "metric": "Trotter steps/s (grouped, c64 amplitudes + FP64 phase), n=28 random k-local",
         "value": round(sps64, 4),
@@ -139,8 +189,9 @@ def main():
                                  "norm_drift_c64": n64 - 1.0, "norm_drift_c128": n128 - 1.0,
                                  "energy_drift_c64": e64 - e0, "energy_drift_c128": e128 - e0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "k_tile<float2,0,true>",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": ROOFLINE_KERNEL,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "bytes_per_launch": bytes_per_launch},
     }
