@@ -238,6 +238,14 @@ typedef struct {
                                   view) and round 0 reads it from LDS; used when
                                   the lowest address bits cannot be round 0's
                                   leading lanes                                */
+    int32_t shift0;            /* 1: round 0's leading lanes (the low address
+                                  bits) have components along round 0's own
+                                  coordinates; lanes_post[0] holds them without
+                                  those components (the layout round 0 writes
+                                  to LDS), and the outputs of round 0, when it
+                                  is not Lambda's round, carry the sign
+                                  (-1)^{k.d}: k the output coordinates, d the
+                                  dropped components of the thread's lanes    */
 } sd_round_view;
 sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int32_t i,
                                 sd_round_view *v);

@@ -81,6 +81,7 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         for (int l = 0; l < 4; ++l) d.io_reg[l] = p.io_reg[l];
         for (int j = 0; j < 4; ++j) d.swz[j] = p.swz[j];
         d.staged = p.staged ? 1 : 0;
+        d.shift0 = p.shift0 ? 1 : 0;
         std::memcpy(buf.data() + i * sizeof(PassDev), &d, sizeof(d));
         uint8_t *t = buf.data() + toff;
         const int m = d.m;
@@ -552,6 +553,29 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             sv[b] = slot(pd.mr[i]) * 16u;
         }
     }
+    // A direct pass whose low address bits (round 0's lanes 0..3) have
+    // components d(t) along round 0's own coordinates: the thread's registers
+    // sit at coordinates shifted by d(t), so the transform of round 0 comes
+    // out as (-1)^{k.d(t)} times the true one at output coordinate k.  Its
+    // outputs are written at k (lanes_post[0] without those components) and,
+    // when round 0 is not Lambda's round, take the sign (-1)^{k.d(t)} after
+    // the forward butterflies and again before the backward ones.  k covers
+    // the 4 register slots after the exchange and the lane bits 4, 5, which
+    // then hold register coordinates 2, 3.  Bit g of sgn0 is the sign of
+    // register g; it is kept in the thread's round-0 read address, which a
+    // direct pass never uses (round 0 reads HBM forward, its write layout
+    // backward).
+    uint32_t sgn0 = 0;
+    if (pd.shift0 && !staged) {
+        uint32_t d = 0;
+        for (int i = 0; i < kLE && i < TL; ++i)
+            if ((tid >> i) & 1) d ^= pd.lanes[0][i] ^ pd.lanes_post[0][i];
+        uint32_t w = 0, kap = 0;
+        for (int l = 0; l < kLE; ++l) w |= ((d >> pd.regpost[0][l]) & 1u) << l;
+        for (int x = 0; x < pd.nx[0]; ++x) kap ^= (tid >> (kLE + x)) & (d >> pd.reg[0][2 + x]) & 1u;
+        for (int g = 0; g < kE; ++g) sgn0 |= ((__popc(g & w) ^ kap) & 1u) << g;
+    }
+    const bool sh0 = pd.shift0 && !staged && nr >= 2;
     // thr[r] = (address the forward round reads, before the lane exchange;
     // address it writes, after the exchange, with the thread's output XOR)
     uint32_t sgnb = 0;  // tile coordinates for the signs of Lambda's terms
@@ -574,7 +598,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             const uint32_t bit = (__popc(pd.B[a] & pd.later[r] & bt) ^ (pd.dflag[r] >> l)) & 1u;
             pm |= bit << a;
         }
-        const uint32_t rd = slot(bt) * 16u;
+        const uint32_t rd = (r == 0 && sh0) ? sgn0 : slot(bt) * 16u;
         if (r == nrounds - 1) {
             sgnb = btp ^ pm;
             thr[r * T_ + tid] = make_uint2(rd, rd);
@@ -703,6 +727,16 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     // The rounds of one tile.  Step 0 takes its input from pre[] and, with
     // PF, then refills pre[] with the next tile's round-0 amplitudes; the
     // last step stores to HBM.  Every step ends with a block barrier.
+    // the sign (-1)^{k.d(t)} of round 0's outputs (see sgn0), flipped in
+    // place in the high words
+    auto apply_sign0 = [&](uint32_t sgn0) {
+#pragma unroll
+        for (int g = 0; g < kE; ++g) {
+            const uint64_t mm = (uint64_t)((sgn0 << (31 - g)) & 0x80000000u) << 32;
+            re[g] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(re[g]) ^ mm));
+            im[g] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(im[g]) ^ mm));
+        }
+    };
     // exchange of register bits 2, 3 with lane bits 4, 5 (nx of them), and
     // butterflies on register bits 2, 3 (nx of them)
     auto xchg = [&](int nx) {
@@ -746,6 +780,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             const int nx = pd.nx[r];
             if (step > 0 || staged) read16(ra, rin);  // (step 0 of a direct pass: in re/im)
             if (!lam) {
+                if (sh0 && last) apply_sign0(ab.x);
                 bfly_fwd<0, false>(re, im);
                 if (GEN) {
                     plain_rest(nb);
@@ -760,6 +795,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                     bfly_fwd<2, false>(re, im);
                     bfly_fwd<3, false>(re, im);
                 }
+                if (sh0 && step == 0) apply_sign0(ab.x);
                 if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
                 __syncthreads();
                 continue;

@@ -43,6 +43,10 @@ struct alignas(256) PassDev {
     uint32_t swz[4];                // LDS slot of t: t ^ sum_j parity(t & swz[j]) << j
     int32_t staged;                 // round 0 reads the tile from LDS, staged in
                                     // pivot order (u_hi, mr), not from HBM
+    int32_t shift0;                 // round 0's lanes 0..3 (lanes) have components
+                                    // along its own coordinates, which its LDS
+                                    // layout (lanes_post) drops: the outputs of
+                                    // a round 0 before Lambda's take a sign
 };
 
 // term arrays at term_off: uint32 zeta[m]; (pad to 8) uint64 ztile[m]; double coef[m]

@@ -22,6 +22,7 @@
 // A group whose tile would exceed the on-chip limit is split into commuting
 // sub-groups (any split is exact: the terms commute), each with its own tile.
 #include <algorithm>
+#include <functional>
 #include <array>
 #include <cmath>
 
@@ -86,10 +87,14 @@ int qform(const std::vector<uint32_t> &B, uint32_t x) {
 // lowest address bits; the chunk of round 0, which moves the tile between HBM
 // and registers, is built from basis vectors none of them depends on (see
 // canonicalize) whenever there are such vectors.
+// low0: span parts of the combinations of those low bits that have no
+// spectator part; round 0 can take the low bits as lanes (direct I/O) only
+// if its chunk meets their span in zero alone.
 // min0: the fewest span coordinates round 0's chunk may have (its register
 // slots can only be filled with spectator coordinates).
 void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<uint32_t> &lowspan,
-                     int min0, std::vector<uint32_t> *f, std::vector<int> *chunks) {
+                     const std::vector<uint32_t> &low0, int min0, std::vector<uint32_t> *f,
+                     std::vector<int> *chunks) {
     std::vector<uint32_t> W, dg, rad;
     std::vector<std::pair<uint32_t, uint32_t>> pairs;
     for (int i = 0; i < rho; ++i) W.push_back(1u << i);
@@ -172,50 +177,108 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<
                 if ((co >> i) & 1) dirty[i] = 1;
         }
     }
-    auto fits_in = [&](const std::vector<uint32_t> &c, uint32_t u) {
-        if ((int)c.size() >= kChunkBits) return false;
-        for (uint32_t w : c)
-            if (bil(B, u, w)) return false;
-        return true;
-    };
-    // Greedy packing into chunks of up to kChunkBits mutually orthogonal
-    // vectors: round 0's chunk first from clean even vectors (when a later
-    // chunk exists), then everything else in order.
-    auto pack = [&](bool clean_first, std::vector<std::vector<uint32_t>> *out) {
-        std::vector<std::vector<uint32_t>> &ch = *out;
-        ch.clear();
-        std::vector<uint32_t> rest;
-        if (clean_first) {
-            ch.push_back({});
-            for (size_t i = 0; i < ev.size(); ++i) {
-                if (!dirty[i] && fits_in(ch[0], ev[i])) ch[0].push_back(ev[i]);
-                else rest.push_back(ev[i]);
+    // Assign the vectors to K chunks of at most kChunkBits each, no two
+    // vectors of one chunk with a nonzero product (a CZ inside a round is
+    // not supported), the odd vector first in the last chunk (the Lambda
+    // round: its S is the pass's only i twiddle).  Round 0's chunk decides
+    // how the tile moves between HBM and registers: made of clean vectors
+    // only, the low address bits are plain lanes of round 0; meeting low0 in
+    // zero alone, they are lanes with a sign correction (shift0); otherwise
+    // the pass is staged through LDS.  The fewest chunks win, then the
+    // cheaper I/O; the chunks before the last are filled to kChunkBits when
+    // possible (their rounds then run the straight-line code).  The products form a matching
+    // (hyperbolic pairs, the odd vector and its partner), so a depth-first
+    // search over at most 13 vectors is quick.
+    const int nv = (int)all.size();
+    const int io = odd ? nv - 1 : -1;
+    std::vector<uint32_t> conf(nv, 0);
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j)
+            if (i != j && bil(B, all[i], all[j])) conf[i] |= 1u << j;
+    // search order: the odd vector, then pairs next to each other, dirty first
+    std::vector<int> order;
+    if (io >= 0) order.push_back(io);
+    {
+        std::vector<char> seen(nv, 0);
+        if (io >= 0) seen[io] = 1;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < nv; ++i) {
+                if (seen[i] || (pass == 0) != (dirty[i] != 0)) continue;
+                seen[i] = 1;
+                order.push_back(i);
+                for (int j = 0; j < nv; ++j)
+                    if (!seen[j] && ((conf[i] >> j) & 1)) {
+                        seen[j] = 1;
+                        order.push_back(j);
+                    }
             }
-            if (ch[0].empty()) ch.clear();
-        } else {
-            rest = ev;
-        }
-        const size_t first_open = ch.size();
-        for (uint32_t u : rest) {
-            if (ch.size() == first_open || !fits_in(ch.back(), u)) ch.push_back({});
-            ch.back().push_back(u);
-        }
-        // the odd vector opens the last chunk (the Lambda round): its S is
-        // the only i twiddle of the pass
-        if (odd) {
-            // (a dirty odd vector does not join a clean round-0 chunk)
-            const bool keep_clean = clean_first && ch.size() == 1 && dirty.back();
-            if (!ch.empty() && !keep_clean && fits_in(ch.back(), odd))
-                ch.back().insert(ch.back().begin(), odd);
-            else
-                ch.push_back({odd});
-        }
+    }
+    std::vector<int> asg(nv, -1);
+    // mode 0: round 0's chunk clean; 1: it meets low0 in zero; 2: anything
+    auto meets_low0 = [&](uint32_t mem0) {
+        Echelon e;
+        for (uint32_t u : low0) e.insert(u);
+        for (int i = 0; i < nv; ++i)
+            if (((mem0 >> i) & 1) && !e.insert(all[i])) return true;
+        return false;
+    };
+    auto search = [&](int K, int mode, const std::vector<int> &cap) -> bool {
+        std::vector<int> size(K, 0);
+        std::vector<uint32_t> mem(K, 0);
+        int budget = 200000;  // node limit (never reached at these sizes)
+        std::function<bool(int)> rec = [&](int t) -> bool {
+            if (--budget < 0) return false;
+            if (t == nv) {
+                for (int r = 0; r < K; ++r)
+                    if (size[r] == 0) return false;
+                return size[0] >= min0 || K == 1;
+            }
+            const int v = order[t];
+            int left = nv - t, room = 0;
+            for (int r = 0; r < K; ++r) room += cap[r] - size[r];
+            if (room < left) return false;
+            for (int r = 0; r < K; ++r) {
+                if (v == io && r != K - 1) continue;
+                if (size[r] >= cap[r] || (mem[r] & conf[v])) continue;
+                if (mode == 0 && r == 0 && dirty[v]) continue;
+                if (mode == 1 && r == 0 && meets_low0(mem[0] | (1u << v))) continue;
+                size[r]++;
+                mem[r] |= 1u << v;
+                asg[v] = r;
+                if (rec(t + 1)) return true;
+                size[r]--;
+                mem[r] &= ~(1u << v);
+                asg[v] = -1;
+            }
+            return false;
+        };
+        return rec(0);
     };
     std::vector<std::vector<uint32_t>> ch;
-    bool any_dirty = false;
-    for (char d : dirty) any_dirty = any_dirty || d;
-    pack(any_dirty, &ch);
-    if (ch.size() > 4 || ch.empty() || (int)ch[0].size() < min0) pack(false, &ch);
+    int bestK = 0;
+    const int kmin = std::max(1, (nv + kChunkBits - 1) / kChunkBits);
+    for (int K = kmin; K <= 4 && !bestK; ++K) {
+        for (int mode = 0; mode < 3 && !bestK; ++mode) {
+            // (a single round is Lambda's: no sign correction there, only the
+            // layout, so "meets low0 in zero" suffices for it as well)
+            // first with the chunks before the last full, then any sizes
+            std::vector<int> exact(K, kChunkBits);
+            exact[K - 1] = nv - kChunkBits * (K - 1);
+            std::vector<int> loose(K, kChunkBits);
+            if (exact[K - 1] >= 1 && search(K, mode, exact)) bestK = K;
+            else if (search(K, mode, loose)) bestK = K;
+        }
+    }
+    if (!bestK) {
+        // (cannot happen for rho <= 4 kChunkBits: a matching splits over two chunks)
+        ch.assign(1, {});
+        for (int i = 0; i < nv; ++i) ch[0].push_back(all[i]);
+    } else {
+        ch.assign(bestK, {});
+        if (io >= 0) ch[bestK - 1].push_back(all[io]);
+        for (int i = 0; i < nv; ++i)
+            if (i != io) ch[asg[i]].push_back(all[i]);
+    }
     f->clear();
     chunks->clear();
     for (auto &c : ch) {
@@ -238,60 +301,28 @@ sd_status canonicalize(PassHost *ps) {
     std::vector<uint32_t> lowspan;
     const uint32_t rmk = (rho >= 32) ? ~0u : ((1u << rho) - 1);
     for (int k = 0; k < p.c && k < 4 && k < (int)p.mr.size(); ++k) lowspan.push_back(p.mr[k] & rmk);
+    std::vector<uint32_t> low0;
+    {
+        const int kk = (int)lowspan.size();
+        for (uint32_t sset = 1; sset < (1u << kk); ++sset) {
+            uint32_t x = 0;
+            for (int k = 0; k < kk; ++k)
+                if ((sset >> k) & 1) x ^= p.mr[k];
+            if (!(x & ~rmk)) low0.push_back(x);
+        }
+    }
     // round 0's register slots not taken by its chunk hold spectators
     // (tiles below the register-round kernel's minimum run the generic kernel)
     const bool rounds = p.D >= 2 * kRegBits + kXBits;
     const int min0 = rounds ? std::min(rho, std::max(0, kRegBits - (p.D - rho))) : 0;
-    canonical_basis(p.B, rho, lowspan, min0, &f, &p.chunk);
+    canonical_basis(p.B, rho, lowspan, low0, min0, &f, &p.chunk);
     if (!p.chunk.empty() && p.chunk[0] < min0)
         return fail(SD_ERR_INTERNAL, "round 0 chunk too small for its register slots");
     if ((int)f.size() != rho) return fail(SD_ERR_INTERNAL, "canonical basis size");
     // Round 0 moves the tile between HBM and registers directly, with its
-    // lanes running over the lowest address bits (coalescing).  A lane vector
-    // must have no component along the round's span coordinates (the
-    // butterflies would see shifted inputs), so the leading low bits' tile
-    // coordinates must lie in the span of the other chunks and the
-    // spectators.  The packing above builds chunk 0 that way when it can;
-    // among the chunks before the Lambda chunk, the one that leaves the
-    // longest run of such low bits goes first.
-    const int nch = (int)p.chunk.size();
-    if (nch >= 2) {
-        int best = 0, best_k = -1, off = 0;
-        std::vector<int> offs;
-        for (int r = 0; r < nch; ++r) {
-            offs.push_back(off);
-            off += p.chunk[r];
-        }
-        // the tile coordinates of address bit k in the new basis are
-        // M^-1 mr[k] on the span part; chunk r's part is its slice
-        std::vector<uint64_t> f64c(f.begin(), f.end());
-        Coords cfc(f64c);
-        const uint32_t rmc = (rho >= 32) ? ~0u : ((1u << rho) - 1);
-        for (int r = 0; r + 1 < nch; ++r) {
-            const uint32_t cm = ((1u << p.chunk[r]) - 1) << offs[r];
-            int k = 0;
-            while (k < p.c && k < (int)p.mr.size()) {
-                uint32_t yn = 0;
-                if (!cfc.solve(p.mr[k] & rmc, &yn) || (yn & cm)) break;
-                ++k;
-            }
-            if (k > best_k) {
-                best_k = k;
-                best = r;
-            }
-        }
-        if (best != 0) {
-            std::vector<uint32_t> g(f.begin() + offs[best], f.begin() + offs[best] + p.chunk[best]);
-            std::vector<int> sizes = {p.chunk[best]};
-            for (int r = 0; r < nch; ++r) {
-                if (r == best) continue;
-                g.insert(g.end(), f.begin() + offs[r], f.begin() + offs[r] + p.chunk[r]);
-                sizes.push_back(p.chunk[r]);
-            }
-            f = g;
-            p.chunk = sizes;
-        }
-    }
+    // lanes running over the lowest address bits (coalescing); the chunk
+    // search above has put in front the chunk that allows it (see
+    // plan_rounds for the lanes).
     std::vector<uint64_t> f64(f.begin(), f.end());
     Coords cf(f64);
     const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
@@ -382,6 +413,7 @@ sd_status plan_rounds(PassHost *ps) {
     p.io_phys.clear();
     p.io_k = 0;
     p.staged = false;
+    p.shift0 = false;
     if (D < 2 * RB + kXBits) {  // tiny tile: handled by the generic kernel only
         p.lam_round = 0;
         p.bucket.assign(33, 0);
@@ -414,7 +446,7 @@ sd_status plan_rounds(PassHost *ps) {
             Echelon e;
             for (int b = off; b < off + s; ++b) e.insert(1ull << b);
             for (int k = 0; k < p.c && k < D; ++k)
-                if ((p.mr[k] & chunkm) || !e.insert(p.mr[k])) break;
+                if (!e.insert(p.mr[k])) break;
             for (int b : cand)
                 if ((int)bits.size() < RB && e.insert(1ull << b)) bits.push_back(b);
         }
@@ -452,13 +484,19 @@ sd_status plan_rounds(PassHost *ps) {
             ln[4 + x] = 1u << p.xl[r][x];
             set[4 + x] = 1;
         }
+        uint32_t chunk0 = 0;  // round 0's own (transformed) coordinates
         if (r == 0) {
-            // direct I/O needs all c leading low bits as clean lanes;
-            // otherwise the tile is staged through LDS in pivot order
-            const uint32_t chunkm = p.chunk.empty() ? 0u : (((1u << chunks[0]) - 1));
+            // Direct I/O needs the c leading low address bits as lanes 0..3,
+            // independent of the round's registers and exchanged lanes;
+            // otherwise the tile is staged through LDS in pivot order.  A low
+            // bit with components along the round's own coordinates shifts
+            // the thread's register frame: the kernel writes the round's
+            // outputs without those components (lanes_post) and corrects
+            // their signs (shift0).
+            chunk0 = p.chunk.empty() ? 0u : (((1u << chunks[0]) - 1));
             Echelon e2 = e;
             int k = 0;
-            while (k < p.c && k < 4 && !(p.mr[k] & chunkm) && e2.insert(p.mr[k])) ++k;
+            while (k < p.c && k < 4 && e2.insert(p.mr[k])) ++k;
             p.staged = k < std::min(p.c, 4);
             p.io_k = p.staged ? 0 : k;
             for (int i = 0; i < p.io_k; ++i) {
@@ -481,6 +519,11 @@ sd_status plan_rounds(PassHost *ps) {
         p.lanes[r] = ln;
         p.lanes_post[r] = ln;
         for (int x = 0; x < p.nx[r]; ++x) p.lanes_post[r][4 + x] = 1u << p.reg[r][2 + x];
+        if (r == 0)
+            for (int i = 0; i < p.io_k; ++i) {
+                p.lanes_post[0][i] = ln[i] & ~chunk0;
+                if (ln[i] & chunk0) p.shift0 = true;
+            }
     }
     auto phys = [&](uint32_t v) {
         uint64_t x = 0;
@@ -496,7 +539,7 @@ sd_status plan_rounds(PassHost *ps) {
     // lanes 0..3 must be independent.
     std::vector<std::array<uint32_t, 4>> quads;
     for (int r = 0; r < nrounds; ++r)
-        quads.push_back({p.lanes[r][0], p.lanes[r][1], p.lanes[r][2], p.lanes[r][3]});
+        quads.push_back({p.lanes_post[r][0], p.lanes_post[r][1], p.lanes_post[r][2], p.lanes_post[r][3]});
     if (p.staged) quads.push_back({p.mr[0], p.mr[1], p.mr[2], p.mr[3]});
     auto lowbits = [](uint32_t v, const uint32_t *m, int nb) {
         uint32_t g = v & ((1u << nb) - 1);
@@ -743,41 +786,73 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         // Sub-groups are grown one at a time: first every remaining term whose
         // X part already lies in the span joins (no growth), then the term
         // whose addition lets the most remaining terms in for free is added.
-        std::vector<std::vector<int64_t>> subs;
-        std::vector<int64_t> rest(groups[g].begin(), groups[g].end());
-        while (!rest.empty()) {
-            Echelon span;
-            for (int q = 0; q < cc; ++q) span.insert(1ull << q);
-            std::vector<int64_t> cur;
-            while (true) {
-                std::vector<int64_t> keep;
-                for (int64_t k : rest) {
-                    if ((int)cur.size() < kMaxPassTerms && span.contains(T[k].x))
-                        cur.push_back(k);
-                    else
-                        keep.push_back(k);
-                }
-                rest.swap(keep);
-                if (rest.empty() || span.dim() >= Dcap || (int)cur.size() >= kMaxPassTerms) break;
-                size_t best = 0;
-                int best_score = -1;
-                for (size_t a = 0; a < rest.size(); ++a) {
-                    Echelon t2 = span;
-                    t2.insert(T[rest[a]].x);
-                    int score = 0;
-                    for (int64_t k : rest)
-                        if (t2.contains(T[k].x)) ++score;
-                    if (score > best_score) {
-                        best_score = score;
-                        best = a;
+        // The growth is repeated with seeded random tie-breaks (and now and
+        // then the second-best term); the split with the fewest sub-groups,
+        // then the fewest register rounds (span dimensions / kChunkBits,
+        // rounded up), is kept.  Every split is exact: the terms commute.
+        auto grow = [&](uint64_t seed) {
+            std::vector<std::vector<int64_t>> subs;
+            std::vector<int64_t> rest(groups[g].begin(), groups[g].end());
+            uint64_t rng = seed;
+            auto next = [&]() {
+                rng ^= rng << 13;
+                rng ^= rng >> 7;
+                rng ^= rng << 17;
+                return rng;
+            };
+            int rounds = 0;
+            while (!rest.empty()) {
+                Echelon span;
+                for (int q = 0; q < cc; ++q) span.insert(1ull << q);
+                std::vector<int64_t> cur;
+                while (true) {
+                    std::vector<int64_t> keep;
+                    for (int64_t k : rest) {
+                        if ((int)cur.size() < kMaxPassTerms && span.contains(T[k].x))
+                            cur.push_back(k);
+                        else
+                            keep.push_back(k);
                     }
+                    rest.swap(keep);
+                    if (rest.empty() || span.dim() >= Dcap || (int)cur.size() >= kMaxPassTerms) break;
+                    size_t best = 0, second = 0;
+                    int best_score = -1, second_score = -1;
+                    for (size_t a = 0; a < rest.size(); ++a) {
+                        Echelon t2 = span;
+                        t2.insert(T[rest[a]].x);
+                        int score = 0;
+                        for (int64_t k : rest)
+                            if (t2.contains(T[k].x)) ++score;
+                        // (seed 0: the plain greedy, first best in term order)
+                        const bool tie = seed && score == best_score && (next() & 1);
+                        if (score > best_score || tie) {
+                            second = best;
+                            second_score = best_score;
+                            best_score = score;
+                            best = a;
+                        } else if (score > second_score) {
+                            second_score = score;
+                            second = a;
+                        }
+                    }
+                    if (seed && second_score >= 0 && (next() % 8) == 0) best = second;
+                    span.insert(T[rest[best]].x);
+                    cur.push_back(rest[best]);
+                    rest.erase(rest.begin() + (long)best);
                 }
-                span.insert(T[rest[best]].x);
-                cur.push_back(rest[best]);
-                rest.erase(rest.begin() + (long)best);
+                rounds += (std::max(1, span.dim() - cc) + kChunkBits - 1) / kChunkBits;
+                subs.push_back(std::move(cur));
             }
-            subs.push_back(std::move(cur));
+            return std::make_pair(subs, rounds);
+        };
+        auto best_split = grow(0);
+        for (uint64_t r = 1; r <= 48 && groups[g].size() > 1; ++r) {
+            auto cand = grow(0x9e3779b97f4a7c15ull * r + g * 0x632be59bd9b4e019ull + 1);
+            if (cand.first.size() < best_split.first.size() ||
+                (cand.first.size() == best_split.first.size() && cand.second < best_split.second))
+                best_split = std::move(cand);
         }
+        std::vector<std::vector<int64_t>> &subs = best_split.first;
         for (auto &s : subs) {
             PassHost ps;
             sd_status st = build_pass(n, T, (int32_t)g, s, Dcap, cc, &ps);

@@ -150,6 +150,9 @@ struct PassHost {
     uint64_t io_reg[4] = {};        // physical offsets of round 0's register slots
     int io_k = 0;                   // leading lanes on the lowest address bits
     bool staged = false;            // tile moves HBM <-> LDS in pivot order instead
+    bool shift0 = false;            // round 0's lanes have components along its own
+                                    // coordinates (lanes_post[0] drops them; the
+                                    // kernel corrects the signs)
     uint32_t swz[4] = {};           // LDS swizzle: slot(t) = t ^ sum_j parity(t & swz[j]) << j
     std::vector<int32_t> bucket;    // 33 offsets: terms sorted by their Lambda
                                     // pattern on the registers of lam_round

@@ -7,7 +7,9 @@ through an on-chip array indexed by the swizzled slot of its tile coordinate.
 A round transforms up to 4 register coordinates, exchanges register bits 2,
 3 with lane bits 4, 5 (a lane permute inside the wave) and transforms the 2
 coordinates brought in.  Round 0 takes its amplitudes from the state vector
-directly and its inverse round writes them back directly.
+directly and its inverse round writes them back directly; when its lanes
+(the lowest address bits) have components along its own coordinates, its
+outputs are laid out without them and take the matching sign.
 The CZ/S layer is not multiplied in: its S factors are i twiddles inside the
 butterflies, and its Z factors and cross-chunk CZ factors are XORs of the
 addresses a forward round writes to and the mirrored inverse round reads from
@@ -159,6 +161,23 @@ def apply_pass(psi, n, ps, rv, tau):
             wr[r] = rd[r]
         else:
             wr[r] = lds_slot(btp ^ pm, swz)
+    # round 0 with low-bit lanes that have components d(t) along its own
+    # coordinates: its outputs are laid out without them (lanes_post[0]) and,
+    # when it is not Lambda's round, carry the sign (-1)^{k.d(t)}
+    sign0 = None
+    if rv.get("shift0", 0) and not staged and nr >= 2:
+        d = np.zeros(T, dtype=np.int64)
+        for i in range(min(4, TL)):
+            d ^= ((tid >> i) & 1) * (rv["lanes"][0][i] ^ rv["lanes_post"][0][i])
+        w = np.zeros(T, dtype=np.int64)
+        for l in range(4):
+            w |= ((d >> rv["regpost"][0][l]) & 1) << l
+        kap = np.zeros(T, dtype=np.int64)
+        for x in range(rv["nx"][0]):
+            kap ^= (tid >> (4 + x)) & (d >> rv["reg"][0][2 + x]) & 1
+        sign0 = np.ones((T, 16))
+        for g in range(16):
+            sign0[:, g] = np.where((_popc(g & w) ^ kap) & 1, -1.0, 1.0)
     rs_pre = [[int(lds_slot(1 << rv["reg"][r][b], swz)) for b in range(4)] for r in range(4)]
     rs_post = [[int(lds_slot(1 << rv["regpost"][r][b], swz)) for b in range(4)] for r in range(4)]
     bucket = rv["bucket"]
@@ -202,10 +221,14 @@ def apply_pass(psi, n, ps, rv, tau):
             nx = rv["nx"][r]
             tw = rv["iflag"][r] & 1
             if not lam:
+                if sign0 is not None and r == 0 and last:
+                    R = R * sign0
                 for L in range(nb):
                     _stage(R, L, 0, True)
                 _xchg(R, nx)
                 _stages_x(R, nx)
+                if sign0 is not None and r == 0 and step == 0:
+                    R = R * sign0
             else:
                 if nb:
                     _stage(R, 0, tw, True)

@@ -367,6 +367,14 @@ def _check_round_structure(ps, rv):
     assert rv["lanes"][0][:k] == [int(v) for v in ps["pivot_coord"][:k]]
     c = min(ps["coalesce_log2"], 4)
     assert (k == c) != bool(rv["staged"])
+    # round 0 writes its outputs without the lanes' components along its own
+    # coordinates; every layout spans the tile
+    nb0 = bin(rv["bmask"][0]).count("1")
+    c0 = sum(1 << a for a in range(nb0 + rv["nx"][0]))
+    assert rv["lanes_post"][0][:k] == [v & ~c0 for v in rv["lanes"][0][:k]]
+    assert bool(rv["shift0"]) == any(v & c0 for v in rv["lanes"][0][:k])
+    for r in range(nr):
+        assert _rank([1 << q for q in rv["regpost"][r]] + list(rv["lanes_post"][r])) == D
 
 
 def _rank(vs):
@@ -424,6 +432,10 @@ def test_register_rounds_models_match_oracle(case, dtype):
     passes, rounds = _export_all(p, dtype)
     for q, r in zip(passes, rounds):
         _check_round_structure(q, r)
+    if case in ("klocal", "wide", "n16"):
+        # these plans include passes whose round-0 lanes are shifted (direct
+        # I/O with the layout and sign correction)
+        assert any(r["shift0"] and not r["staged"] and r["n_rounds"] >= 2 for r in rounds)
     psi0 = workloads.random_state(m.n, 3)
     got = round_emulator.evolve(psi0, m.n, passes, rounds, info.n_groups, 0.11, 1, 2)
     want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.11, 1, 2)
@@ -442,3 +454,4 @@ def test_register_round_structure_full_size(which):
         for q, r in zip(passes, rounds):
             if q["tile_log2"] >= 10:
                 _check_round_structure(q, r)
+
