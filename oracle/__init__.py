@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     schedule,
     evolve,
     evolve_terms_dense,
+    apply_on_coset,
     energy,
     fidelity,
     lib,

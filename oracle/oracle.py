@@ -25,6 +25,9 @@ What it computes (plain definitions, no Clifford, tableau or diagonal form):
   P|x> = i^{#Y} (-1)^{popcount(x & zmask)} |x ^ xmask>, evaluated in FP64 in
   ``csrc/oracle.c``.
 * Energy E = sum_j c_j <psi|P_j|psi>;  fidelity F = |<a|b>|^2 / (|a|^2 |b|^2).
+* apply_on_coset: the same rotations on the amplitudes of one coset of the
+  span of a commuting group's X masks (which the group maps onto itself), for
+  sampled outputs of states too large for the full-state loops.
 """
 from __future__ import annotations
 
@@ -214,6 +217,55 @@ def evolve_terms_dense(n: int, xs, zs, thetas, psi0: np.ndarray) -> np.ndarray:
                              xs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                              zs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                              _dp(th))
+    return psi
+
+
+def apply_on_coset(xs, zs, thetas, x0: int, span, amps) -> np.ndarray:
+    """exp(-i theta_k P_k) applied in the given order (first acts first) to the
+    amplitudes of a state on one coset C = {x0 ^ (XOR of span[i] over the set
+    bits i of j)} of a subspace that holds every X mask; amps[j] is the
+    amplitude at that index.  Each P_k maps C onto itself (x -> x ^ xmask_k),
+    so the output on C depends on amps alone: the same rotation as the
+    full-state loops, e^{-i theta P} = cos(theta) - i sin(theta) P with
+    (P psi)[y] = i^{popcount(xmask & zmask)} (-1)^{popcount((y ^ xmask) & zmask)}
+    psi[y ^ xmask], restricted to C.  FP64.  Used for sampled outputs of
+    states too large for the full-state loops."""
+    span = [int(v) for v in span]
+    r = len(span)
+    # echelon form of the span with each row's combination of span[i]
+    rows = []
+    for i, v in enumerate(span):
+        comb = 1 << i
+        for rv, rc in rows:
+            if v ^ rv < v:
+                v, comb = v ^ rv, comb ^ rc
+        if v == 0:
+            raise ValueError("span vectors must be independent")
+        rows.append((v, comb))
+        rows.sort(reverse=True)
+
+    def coords(x: int) -> int:
+        comb = 0
+        for rv, rc in rows:
+            if x ^ rv < x:
+                x, comb = x ^ rv, comb ^ rc
+        if x != 0:
+            raise ValueError("X mask outside the span")
+        return comb
+
+    j = np.arange(1 << r, dtype=np.int64)
+    phys = np.full(1 << r, np.uint64(x0), dtype=np.uint64)
+    for i, v in enumerate(span):
+        phys ^= ((j >> i) & 1).astype(np.uint64) * np.uint64(v)
+    psi = np.asarray(amps, dtype=np.complex128).copy()
+    for x, z, th in zip(xs, zs, thetas):
+        x, z = int(x), int(z)
+        a = coords(x)
+        src = j ^ a
+        ny = bin(x & z).count("1")
+        par = np.bitwise_count(phys[src] & np.uint64(z)) & 1
+        ppsi = (1j ** ny) * np.where(par == 1, -1.0, 1.0) * psi[src]
+        psi = np.cos(th) * psi - 1j * np.sin(th) * ppsi
     return psi
 
 

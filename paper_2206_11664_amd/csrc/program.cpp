@@ -846,7 +846,17 @@ sd_status compile_program(int n, const std::vector<Term> &T,
             return std::make_pair(subs, rounds);
         };
         auto best_split = grow(0);
-        for (uint64_t r = 1; r <= 48 && groups[g].size() > 1; ++r) {
+        // (no restarts when the plain greedy meets the bound set by the
+        // dimension of the group's X span with the low bits)
+        size_t lb = 1;
+        {
+            Echelon all;
+            for (int q = 0; q < cc; ++q) all.insert(1ull << q);
+            for (int64_t k : groups[g]) all.insert(T[k].x);
+            const int room = std::max(1, Dcap - cc);
+            lb = (size_t)std::max(1, (all.dim() - cc + room - 1) / room);
+        }
+        for (uint64_t r = 1; r <= 48 && groups[g].size() > 1 && best_split.first.size() > lb; ++r) {
             auto cand = grow(0x9e3779b97f4a7c15ull * r + g * 0x632be59bd9b4e019ull + 1);
             if (cand.first.size() < best_split.first.size() ||
                 (cand.first.size() == best_split.first.size() && cand.second < best_split.second))

@@ -309,3 +309,144 @@ def test_state_above_4gib_uses_wide_offsets():
     diff = float(torch.linalg.vector_norm(c.to(torch.complex128) - b))
     print(f"[gpu] n29 c64 vs c128 L2={diff:.3e}", flush=True)
     assert diff < 1e-5
+
+
+def _gpu_fidelity(a, b, n):
+    ov = sd.sd_inner(a, b, n)
+    return abs(ov) ** 2 / (sd.sd_norm2(a, n) * sd.sd_norm2(b, n))
+
+
+def test_config2_xxz_n26_full_length():
+    # periodic XXZ n = 26 from the Neel state, second order, dt = 0.05: one
+    # step of the complex128 path against the oracle on the full vector, then
+    # 1000 steps of both paths (the complex64 bar: L2 <= 1e-5 and fidelity
+    # >= 1 - 1e-6 against the FP64 path)
+    m = workloads.xxz_chain(n=26)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    print(f"[gpu] xxz26 groups {plan.info.n_groups} passes c64 {plan.info.passes_c64}", flush=True)
+    psi0 = m.initial_state()
+    want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.05, 1, 2)
+    d = torch.from_numpy(psi0).cuda()
+    plan.evolve(d, 0.05, 1, 2)
+    err = l2(d.cpu().numpy(), want)
+    print(f"[gpu] xxz26 one step c128 L2={err:.3e}", flush=True)
+    assert err <= 1e-10
+    del want
+    a128 = torch.from_numpy(psi0).cuda()
+    a64 = a128.to(torch.complex64)
+    plan.evolve(a128, 0.05, 1000, 2)
+    plan.evolve(a64, 0.05, 1000, 2)
+    torch.cuda.synchronize()
+    b64 = a64.to(torch.complex128)
+    fid = _gpu_fidelity(a128, b64, 26)
+    err = float(torch.linalg.vector_norm(b64 - a128))
+    drift = abs(sd.sd_norm2(a128, 26) - 1.0)
+    print(f"[gpu] xxz26 1000 steps c64 vs c128: L2={err:.3e} 1-F={1 - fid:.3e} "
+          f"c128 norm drift={drift:.2e}", flush=True)
+    assert err <= 1e-5 and fid >= 1 - 1e-6 and drift <= 1e-10
+
+
+def test_config4_full_ensemble():
+    # 256 open XXZ chains, n ~ U{14..20}, 500 second-order steps at dt = 0.05
+    # in one ensemble: complex64 against complex128 for every instance, and
+    # the two smallest instances of both against the oracle
+    models = workloads.xxz_ensemble()
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in models]
+    print(f"[gpu] ensemble of {len(models)}, amplitudes {sum(1 << m.n for m in models)}", flush=True)
+    out = {}
+    for dtype in (sd.SD_C128, sd.SD_C64):
+        ens = sd.sd_ensemble_create([p.p for p in plans], dtype)
+        ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+        sd.sd_ensemble_bind_workspace(ens, ws)
+        states = [torch.from_numpy(m.initial_state()).to(TDT[dtype]).cuda() for m in models]
+        sd.sd_ensemble_evolve(ens, states, 0.05, 500, 2)
+        torch.cuda.synchronize()
+        sd.sd_ensemble_destroy(ens)
+        out[dtype] = states
+    fids = [_gpu_fidelity(a, b.to(torch.complex128), m.n)
+            for m, a, b in zip(models, out[sd.SD_C128], out[sd.SD_C64])]
+    print(f"[gpu] ensemble c64 vs c128: mean 1-F {1 - np.mean(fids):.3e}, "
+          f"max 1-F {1 - min(fids):.3e}", flush=True)
+    assert min(fids) >= 1 - 1e-6
+    for i in sorted(range(len(models)), key=lambda i: models[i].n)[:2]:
+        m = models[i]
+        want = oracle.evolve(m.n, m.paulis, m.coeffs, m.initial_state(), 0.05, 500, 2)
+        e128 = l2(out[sd.SD_C128][i].cpu().numpy(), want)
+        e64 = l2(out[sd.SD_C64][i].cpu().numpy().astype(np.complex128), want)
+        print(f"[gpu] ensemble instance {i} n={m.n}: L2 c128 {e128:.3e} c64 {e64:.3e}", flush=True)
+        assert e128 <= 1e-10 and e64 <= 1e-5
+
+
+def _xspan_basis(xs):
+    rows, basis = [], []
+    for v in xs:
+        w = int(v)
+        for r in rows:
+            w = min(w, w ^ r)
+        if w:
+            rows.append(w)
+            basis.append(int(v))
+    return basis
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C64, sd.SD_C128])
+def test_config5_jw_n32_sampled_cosets(dtype):
+    # the Jordan-Wigner workload at its full size, n = 32 (32 GiB complex64,
+    # 64 GiB complex128, 64-bit in-state offsets): one application of its
+    # largest group with an X span of rank <= 14 on a random state; sampled
+    # outputs (whole cosets of the X span, which the group maps onto itself)
+    # against the oracle computed on those cosets alone
+    n = 32
+    m = workloads.jw_fermionic(n=n)
+    full = sd.Plan(n, m.paulis, m.coeffs)
+    t = oracle.build_terms(n, m.paulis, m.coeffs)
+    best = None
+    for g in range(full.info.n_groups):
+        ids = list(full.group(g).term_ids)
+        r = len(_xspan_basis([t.x[k] for k in ids]))
+        if 8 <= r <= 14 and (best is None or len(ids) > len(best[1])):
+            best = (g, ids, r)
+    g, ids, r = best
+    letters = {(0, 0): "I", (1, 0): "X", (0, 1): "Z", (1, 1): "Y"}
+    ps = ["".join(letters[((int(t.x[k]) >> q) & 1, (int(t.z[k]) >> q) & 1)] for q in range(n))
+          for k in ids]
+    cs = [float(t.c[k]) for k in ids]
+    plan = sd.Plan(n, ps, cs).bind()
+    assert plan.info.n_groups == 1
+    print(f"[gpu] jw32 group {g}: {len(ids)} terms, X rank {r}, dtype={dtype}, "
+          f"passes {[p['rho'] for p in plan.passes(dtype)]}", flush=True)
+    psi = torch.empty(1 << n, dtype=TDT[dtype], device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(32)
+    flat = torch.view_as_real(psi).view(-1)
+    chunk = 1 << 28
+    for s in range(0, flat.numel(), chunk):
+        flat[s:s + chunk].normal_(generator=gen)
+    del flat
+    span = _xspan_basis([t.x[k] for k in ids])
+    rng = np.random.default_rng(33)
+    x0s = [int(v) for v in rng.integers(0, 1 << n, size=6, dtype=np.uint64)]
+    jj = np.arange(1 << len(span), dtype=np.int64)
+    idx = []
+    for x0 in x0s:
+        v = np.full(jj.shape, x0, dtype=np.int64)
+        for i, b in enumerate(span):
+            v ^= ((jj >> i) & 1) * b
+        idx.append(v)
+    idx_t = torch.from_numpy(np.concatenate(idx)).cuda()
+    before = psi[idx_t].cpu().numpy().astype(np.complex128)
+    dt = 0.02
+    plan.evolve(psi, dt, 1, 1)
+    after = psi[idx_t].cpu().numpy().astype(np.complex128)
+    torch.cuda.synchronize()
+    del psi
+    xs = [int(t.x[k]) for k in ids]
+    zs = [int(t.z[k]) for k in ids]
+    th = [float(t.c[k]) * dt for k in ids]
+    L = 1 << len(span)
+    worst = 0.0
+    for c, x0 in enumerate(x0s):
+        want = oracle.apply_on_coset(xs, zs, th, x0, span, before[c * L:(c + 1) * L])
+        got = after[c * L:(c + 1) * L]
+        worst = max(worst, float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+    print(f"[gpu] jw32 sampled cosets: worst relative L2 {worst:.3e}", flush=True)
+    assert worst <= (1e-12 if dtype == sd.SD_C128 else 1e-6)

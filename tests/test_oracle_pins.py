@@ -241,3 +241,56 @@ def test_fidelity():
     assert abs(oracle.fidelity(a, 2j * a) - 1) < 1e-14
     b = workloads.random_state(5, 2)
     assert oracle.fidelity(a, b) < 0.5
+
+
+# --- sampled outputs on a coset: pinned to the full-state rotation loops ----
+@pytest.mark.parametrize("seed,rho,extra", [(1, 4, 0), (2, 6, 1), (3, 7, 2)])
+def test_apply_on_coset_matches_full_state(seed, rho, extra):
+    # a commuting group with Y, Z and X factors; the coset basis is given as
+    # random combinations of the X span (plus `extra` further vectors, a
+    # larger invariant subspace), so the coordinates of each X mask are not
+    # read off directly
+    from tests import groups
+    rng = np.random.default_rng(seed)
+    n = 10
+    ps, cs = groups.commuting_group(rng, n, rho, 14)
+    t = oracle.build_terms(n, ps, cs)
+    xs = [int(v) for v in t.x]
+    zs = [int(v) for v in t.z]
+    thetas = list(0.37 * t.c)
+    basis = []
+
+    def indep(v, vs):
+        rows = []
+        for w in vs + [v]:
+            for r in rows:
+                w = min(w, w ^ r)
+            if w == 0:
+                return False
+            rows.append(w)
+        return True
+
+    for v in xs:
+        if v and indep(v, basis):
+            basis.append(v)
+    while len(basis) < rho + extra:
+        v = int(rng.integers(1, 1 << n))
+        if indep(v, basis):
+            basis.append(v)
+    # random invertible recombination of the basis
+    mixed = list(basis)
+    for _ in range(20):
+        i, j = rng.choice(len(mixed), 2, replace=False)
+        mixed[i] ^= mixed[j]
+    psi = workloads.random_state(n, seed)
+    full = oracle.evolve_terms_dense(n, xs, zs, thetas, psi)
+    for x0 in rng.integers(0, 1 << n, size=4):
+        idx = np.zeros(1 << len(mixed), dtype=np.int64)
+        for jj in range(1 << len(mixed)):
+            v = int(x0)
+            for i, b in enumerate(mixed):
+                if (jj >> i) & 1:
+                    v ^= b
+            idx[jj] = v
+        got = oracle.apply_on_coset(xs, zs, thetas, int(x0), mixed, psi[idx])
+        assert np.abs(got - full[idx]).max() < 1e-13
