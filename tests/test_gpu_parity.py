@@ -450,3 +450,15 @@ def test_config5_jw_n32_sampled_cosets(dtype):
         worst = max(worst, float(np.linalg.norm(got - want) / np.linalg.norm(want)))
     print(f"[gpu] jw32 sampled cosets: worst relative L2 {worst:.3e}", flush=True)
     assert worst <= (1e-12 if dtype == sd.SD_C128 else 1e-6)
+
+
+@pytest.mark.parametrize("n,steps", [(12, 5), (20, 1)])
+@pytest.mark.parametrize("mode", [sd.SD_MODE_TILES, sd.SD_MODE_PAPER_LAYERS, sd.SD_MODE_TERMWISE])
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_tfim_fully_connected_modes(n, steps, mode, dtype):
+    # the paper's first experiment (fully connected TFIM, two groups): the
+    # fused tiles, the layer-by-layer circuit and the term-by-term baseline,
+    # each against the oracle
+    m = workloads.tfim_fully_connected(n)
+    psi0 = workloads.random_state(n, 12)
+    check(m, dtype, m.dt, steps, 1, dict(mode=mode), psi0=psi0)
