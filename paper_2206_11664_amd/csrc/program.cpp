@@ -23,6 +23,7 @@
 // sub-groups (any split is exact: the terms commute), each with its own tile.
 #include <algorithm>
 #include <functional>
+#include <unordered_map>
 #include <array>
 #include <cmath>
 
@@ -815,14 +816,20 @@ sd_status compile_program(int n, const std::vector<Term> &T,
                     }
                     rest.swap(keep);
                     if (rest.empty() || span.dim() >= Dcap || (int)cur.size() >= kMaxPassTerms) break;
+                    // Adding x_a brings in exactly the terms whose X part has
+                    // the same remainder modulo the span (the echelon basis is
+                    // fully reduced, so the remainder is the coset's unique
+                    // representative): the score is a count of equal remainders.
+                    std::vector<uint64_t> rem(rest.size());
+                    std::unordered_map<uint64_t, int> count;
+                    for (size_t a = 0; a < rest.size(); ++a) {
+                        rem[a] = span.reduce(T[rest[a]].x);
+                        ++count[rem[a]];
+                    }
                     size_t best = 0, second = 0;
                     int best_score = -1, second_score = -1;
                     for (size_t a = 0; a < rest.size(); ++a) {
-                        Echelon t2 = span;
-                        t2.insert(T[rest[a]].x);
-                        int score = 0;
-                        for (int64_t k : rest)
-                            if (t2.contains(T[k].x)) ++score;
+                        const int score = count[rem[a]];
                         // (seed 0: the plain greedy, first best in term order)
                         const bool tie = seed && score == best_score && (next() & 1);
                         if (score > best_score || tie) {
@@ -856,7 +863,10 @@ sd_status compile_program(int n, const std::vector<Term> &T,
             const int room = std::max(1, Dcap - cc);
             lb = (size_t)std::max(1, (all.dim() - cc + room - 1) / room);
         }
-        for (uint64_t r = 1; r <= 48 && groups[g].size() > 1 && best_split.first.size() > lb; ++r) {
+        // (each restart costs about size^2 reductions: fewer for big groups)
+        const size_t gs = groups[g].size();
+        const uint64_t restarts = std::max<uint64_t>(4, std::min<uint64_t>(48, 40000 / (gs * gs + 1)));
+        for (uint64_t r = 1; r <= restarts && gs > 1 && best_split.first.size() > lb; ++r) {
             auto cand = grow(0x9e3779b97f4a7c15ull * r + g * 0x632be59bd9b4e019ull + 1);
             if (cand.first.size() < best_split.first.size() ||
                 (cand.first.size() == best_split.first.size() && cand.second < best_split.second))

@@ -462,3 +462,13 @@ def test_tfim_fully_connected_modes(n, steps, mode, dtype):
     m = workloads.tfim_fully_connected(n)
     psi0 = workloads.random_state(n, 12)
     check(m, dtype, m.dt, steps, 1, dict(mode=mode), psi0=psi0)
+
+
+@pytest.mark.parametrize("n", [6, 8])
+@pytest.mark.parametrize("mode", [sd.SD_MODE_TILES, sd.SD_MODE_PAPER_LAYERS, sd.SD_MODE_TERMWISE])
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_syk_majorana_modes(n, mode, dtype):
+    # the paper's second experiment (SYK Majorana model, C(2n, 4) terms in
+    # many small groups): every execution mode against the oracle
+    m = workloads.syk_majorana(n)
+    check(m, dtype, m.dt, 2, 1, dict(mode=mode), psi0=m.initial_state())

@@ -294,3 +294,27 @@ def test_apply_on_coset_matches_full_state(seed, rho, extra):
             idx[jj] = v
         got = oracle.apply_on_coset(xs, zs, thetas, int(x0), mixed, psi[idx])
         assert np.abs(got - full[idx]).max() < 1e-13
+
+
+# --- the SYK workload (the paper's second experiment) -----------------------
+def test_syk_majorana_terms_match_dense_products():
+    # Jordan-Wigner Majoranas built as dense matrices: they anticommute and
+    # square to one, and every generated term equals g_abcd c_a c_b c_c c_d
+    import math
+    n = 3
+    c = []
+    for q in range(n):
+        zs = {p: dense.Z for p in range(q)}
+        c.append(dense.kron_ops(n, {**zs, q: dense.X}))
+        c.append(dense.kron_ops(n, {**zs, q: dense.Y}))
+    eye = np.eye(1 << n)
+    for a in range(2 * n):
+        for b in range(2 * n):
+            assert np.allclose(c[a] @ c[b] + c[b] @ c[a], 2 * eye * (a == b))
+    m = workloads.syk_majorana(n, seed=6)
+    assert m.m == math.comb(2 * n, 4)
+    g = np.random.default_rng(6).normal(size=m.m)
+    for t, quad in enumerate(itertools.combinations(range(2 * n), 4)):
+        prod = c[quad[0]] @ c[quad[1]] @ c[quad[2]] @ c[quad[3]]
+        assert np.allclose(m.coeffs[t] * dense.pauli_matrix(m.paulis[t]), g[t] * prod)
+    assert workloads.syk_majorana(6).m == math.comb(12, 4)

@@ -14,6 +14,7 @@ from .hamiltonians import (  # noqa: F401
     random_klocal,
     jw_fermionic,
     tfim_fully_connected,
+    syk_majorana,
     xxz_ensemble,
     neel_state,
     basis_state,

@@ -237,6 +237,51 @@ def tfim_fully_connected(n: int, seed: int = 0, dt: float = 0.01) -> Model:
                  steps=1, order=1, init="zero")
 
 
+def _majorana(q: int, y: bool):
+    """Jordan-Wigner Majorana on qubit q (0-based) as i^k X^x Z^z (per qubit,
+    X^x_q Z^z_q): Z on the qubits below q, then X (k = 0) or Y = i X Z
+    (k = 1) on qubit q."""
+    below = (1 << q) - 1
+    return (1 if y else 0, 1 << q, below | ((1 << q) if y else 0))
+
+
+def syk_majorana(n: int, seed: int = 6, dt: float = 0.01) -> Model:
+    """SYK Majorana model of the paper's second experiment on n qubits:
+    H = sum_{a<b<c<d} g_abcd c_a c_b c_c c_d over the 2n Jordan-Wigner
+    Majoranas c_{2q} = Z_0..Z_{q-1} X_q, c_{2q+1} = Z_0..Z_{q-1} Y_q.
+
+    The paper draws J_ijkl complex Gaussian with J_ijkl = -J_jikl = -J_ijlk =
+    J*_lkji and sums over all orderings; collecting the orderings of four
+    distinct Majoranas onto c_a c_b c_c c_d (a < b < c < d) leaves one real
+    coefficient per 4-subset, and the product is a Hermitian Pauli string up
+    to a sign.  Reading used here: that real coefficient is drawn directly,
+    g ~ N(0, 1) from default_rng(seed) in lexicographic (a, b, c, d) order;
+    the sign of the product goes into the coefficient.  C(2n, 4) terms
+    (367,290 at n = 28)."""
+    import itertools
+    rng = np.random.default_rng(seed)
+    quads = list(itertools.combinations(range(2 * n), 4))
+    g = rng.normal(size=len(quads))
+    maj = [_majorana(a // 2, a % 2 == 1) for a in range(2 * n)]
+    letters = {(0, 0): "I", (1, 0): "X", (0, 1): "Z", (1, 1): "Y"}
+    paulis, coeffs = [], []
+    for t, quad in enumerate(quads):
+        k, x, z = 0, 0, 0
+        for a in quad:
+            k2, x2, z2 = maj[a]
+            # (i^k X^x Z^z)(i^k2 X^x2 Z^z2) = i^{k+k2} (-1)^{z.x2} X^{x^x2} Z^{z^z2}
+            k = (k + k2 + 2 * (bin(z & x2).count("1") & 1)) & 3
+            x ^= x2
+            z ^= z2
+        # i^k X^x Z^z = i^{k - |x&z|} P with P the Hermitian string (Y = i X Z)
+        e = (k - bin(x & z).count("1")) & 3
+        assert e in (0, 2), "a product of four distinct Majoranas is Hermitian"
+        paulis.append("".join(letters[((x >> q) & 1, (z >> q) & 1)] for q in range(n)))
+        coeffs.append(float(g[t]) * (1.0 if e == 0 else -1.0))
+    return Model("syk_majorana", n, paulis, np.array(coeffs), dt=dt, steps=1, order=1,
+                 init="random", init_seed=seed + 100)
+
+
 def xxz_ensemble(count: int = 256, seed: int = 4, nmin: int = 14, nmax: int = 20,
                  dt: float = 0.05, steps: int = 500) -> List[Model]:
     """Disorder ensemble of open XXZ chains of uneven size.  From
