@@ -263,10 +263,12 @@ void sd_plan_destroy(sd_plan_t *p);
 sd_status sd_bind_workspace(sd_plan_t *p, void *dev_ptr, size_t bytes, void *stream);
 
 /* state <- (prod over the step schedule of C_g^dagger exp(-i tau Lambda_g) C_g)^steps
-   state, Eq. trotter_simul_diag, with tau = dt (order 1: groups 0..K-1) or the
-   symmetric sequence dt/2 (0..K-2), dt (K-1), dt/2 (K-2..0) for order 2.
+   state, Eq. trotter_simul_diag, with tau = dt (order 1: groups 0..K-1), the
+   symmetric sequence dt/2 (0..K-2), dt (K-1), dt/2 (K-2..0) for order 2, or
+   for order 4 Suzuki's fractal of five order-2 sequences at p dt, p dt,
+   (1-4p) dt, p dt, p dt with p = 1/(4 - 4^(1/3)) (boundaries not merged).
    Asynchronous on `stream`.  state: device pointer to 2^n amplitudes of
-   `dtype`.  Errors: SD_ERR_ARG (order not 1/2, steps < 0, non-finite dt),
+   `dtype`.  Errors: SD_ERR_ARG (order not 1/2/4, steps < 0, non-finite dt),
    SD_ERR_WORKSPACE (no workspace), SD_ERR_HIP. */
 sd_status sd_evolve(const sd_plan_t *p, void *state, sd_dtype dtype, double dt,
                     int64_t steps, int32_t order, void *stream);

@@ -21,6 +21,9 @@ What it computes (plain definitions, no Clifford, tableau or diagonal form):
 * Second order (not specified by the paper, which only cites Suzuki): the
   symmetric Strang sequence -- groups 0..K-2 at dt/2, group K-1 at dt,
   groups K-2..0 at dt/2.  No half steps are merged across step boundaries.
+* Fourth order: Suzuki's fractal composition of five second-order steps,
+  S2(p dt) S2(p dt) S2((1-4p) dt) S2(p dt) S2(p dt), p = 1/(4 - 4^(1/3)),
+  again without merging.
 * e^{-i theta P} psi = cos(theta) psi - i sin(theta) P psi (P^2 = I), with
   P|x> = i^{#Y} (-1)^{popcount(x & zmask)} |x ^ xmask>, evaluated in FP64 in
   ``csrc/oracle.c``.
@@ -172,7 +175,13 @@ def schedule(n_groups: int, order: int) -> List[Tuple[int, float]]:
         seq.append((n_groups - 1, 1.0))
         seq += [(g, 0.5) for g in range(n_groups - 2, -1, -1)]
         return seq
-    raise ValueError("order must be 1 or 2")
+    if order == 4:
+        # Suzuki's fourth-order fractal: S2(p) S2(p) S2(1 - 4p) S2(p) S2(p),
+        # p = 1 / (4 - 4^(1/3)), each S2 the sequence above (no merging)
+        p = 1.0 / (4.0 - 4.0 ** (1.0 / 3.0))
+        s2 = schedule(n_groups, 2)
+        return [(g, f * w) for w in (p, p, 1.0 - 4.0 * p, p, p) for g, f in s2]
+    raise ValueError("order must be 1, 2 or 4")
 
 
 def _dp(a: np.ndarray):

@@ -1163,9 +1163,17 @@ static sd_status launch_pass(const sd_plan_t *p, sd_dtype dt, int i, void *state
     return hip_check(hipGetLastError(), "k_pass launch");
 }
 
+// Group applications of one step as (group, fraction of dt): order 1 the
+// groups in order; order 2 the symmetric (Strang) sequence; order 4 Suzuki's
+// fractal S2(p) S2(p) S2(1 - 4p) S2(p) S2(p), p = 1 / (4 - 4^(1/3)), with the
+// second-order sequences not merged at their boundaries.
 static std::vector<std::pair<int, double>> step_schedule(int K, int order) {
     std::vector<std::pair<int, double>> seq;
-    if (order == 1 || K == 1) {
+    if (order == 4) {
+        const double p = 1.0 / (4.0 - std::cbrt(4.0));
+        for (double w : {p, p, 1.0 - 4.0 * p, p, p})
+            for (auto &gf : step_schedule(K, 2)) seq.push_back({gf.first, gf.second * w});
+    } else if (order == 1 || K == 1) {
         for (int g = 0; g < K; ++g) seq.push_back({g, 1.0});
     } else {
         for (int g = 0; g < K - 1; ++g) seq.push_back({g, 0.5});
@@ -1215,7 +1223,8 @@ extern "C" sd_status sd_evolve(const sd_plan_t *p, void *state, sd_dtype dtype, 
                                int64_t steps, int32_t order, void *stream) {
     if (!p || !state) return fail(SD_ERR_ARG, "sd_evolve: null argument");
     if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_evolve: bad dtype");
-    if (order != 1 && order != 2) return fail(SD_ERR_ARG, "sd_evolve: order must be 1 or 2");
+    if (order != 1 && order != 2 && order != 4)
+        return fail(SD_ERR_ARG, "sd_evolve: order must be 1, 2 or 4");
     if (steps < 0) return fail(SD_ERR_ARG, "sd_evolve: steps < 0");
     if (!std::isfinite(dt)) return fail(SD_ERR_ARG, "sd_evolve: non-finite dt");
     if (!p->bound) return fail(SD_ERR_WORKSPACE, "sd_evolve: no workspace bound");
@@ -1532,7 +1541,8 @@ sd_status launch_levels(sd_ensemble *e, const std::vector<LevelLaunch> &launches
 extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, double dt, int64_t steps,
                                         int32_t order, void *stream) {
     if (!e || !states) return fail(SD_ERR_ARG, "sd_ensemble_evolve: null argument");
-    if (order != 1 && order != 2) return fail(SD_ERR_ARG, "sd_ensemble_evolve: order must be 1 or 2");
+    if (order != 1 && order != 2 && order != 4)
+        return fail(SD_ERR_ARG, "sd_ensemble_evolve: order must be 1, 2 or 4");
     if (steps < 0 || !std::isfinite(dt)) return fail(SD_ERR_ARG, "sd_ensemble_evolve: bad steps/dt");
     if (!e->ws) return fail(SD_ERR_WORKSPACE, "sd_ensemble_evolve: no workspace bound");
     for (size_t i = 0; i < e->plans.size(); ++i) {

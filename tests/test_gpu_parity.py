@@ -74,6 +74,18 @@ def test_random_klocal_reduced(dtype):
 
 
 @pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_fourth_order_suzuki(dtype):
+    # Suzuki's fourth-order fractal of Strang steps, against the oracle's own
+    # schedule (several groups, and a single group)
+    m = workloads.random_klocal(n=12, m=120, seed=31, init_seed=32)
+    check(m, dtype, 0.07, 3, 4)
+    m1 = workloads.xxz_chain(n=10, steps=2)
+    m1.paulis = m1.paulis[: len(m1.paulis) // 4]
+    m1.coeffs = m1.coeffs[: len(m1.paulis)]
+    check(m1, dtype, 0.05, 2, 4)
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
 def test_jw_fermionic_reduced(dtype):
     m = workloads.jw_fermionic(n=12, total=700)
     check(m, dtype, 0.02, 5, 2, psi0=workloads.random_state(12, 5))

@@ -129,14 +129,15 @@ def test_single_commuting_group_is_exact():
         assert np.abs(got - ref).max() < 1e-12
 
 
-@pytest.mark.parametrize("order,slope", [(1, 2.0), (2, 4.0)])
-def test_trotter_error_order(order, slope):
+@pytest.mark.parametrize("order,slope,n0", [(1, 2.0, 40), (2, 4.0, 40), (4, 16.0, 8)])
+def test_trotter_error_order(order, slope, n0):
+    # global error ~ dt^order: halving dt divides it by 2^order
     m = workloads.tfim_chain(6)
     psi0 = m.initial_state()
     T = 0.8
     ref = dense.expm(-1j * T * dense.hamiltonian(m.paulis, m.coeffs)) @ psi0
     errs = []
-    for steps in (40, 80):
+    for steps in (n0, 2 * n0):
         got = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, T / steps, steps, order)
         errs.append(np.linalg.norm(got - ref))
     ratio = errs[0] / errs[1]
@@ -318,3 +319,14 @@ def test_syk_majorana_terms_match_dense_products():
         prod = c[quad[0]] @ c[quad[1]] @ c[quad[2]] @ c[quad[3]]
         assert np.allclose(m.coeffs[t] * dense.pauli_matrix(m.paulis[t]), g[t] * prod)
     assert workloads.syk_majorana(6).m == math.comb(12, 4)
+
+
+def test_fourth_order_schedule_is_symmetric_and_sums_to_dt():
+    # Suzuki's fractal: every group's fractions add up to one step, and the
+    # sequence reads the same backwards (a symmetric product formula)
+    for K in (1, 2, 5):
+        seq = oracle.schedule(K, 4)
+        for g in range(K):
+            assert abs(sum(f for h, f in seq if h == g) - 1.0) < 1e-14
+        assert [h for h, _ in seq] == [h for h, _ in reversed(seq)]
+        assert all(abs(a[1] - b[1]) < 1e-15 for a, b in zip(seq, reversed(seq)))
