@@ -280,6 +280,20 @@ sd_status sd_evolve(const sd_plan_t *p, void *state, sd_dtype dtype, double dt,
 sd_status sd_expectation(const sd_plan_t *p, const void *state, sd_dtype dtype,
                          double *energy, void *stream);
 
+/* out[k] = <psi|P_k|psi> (not normalised) for every merged term k of the
+   plan's Hamiltonian (the order of sd_hamiltonian_terms): the grouped
+   measurement of Sec. "Partitioning Hamiltonian Terms" -- one transform per
+   (sub-)group, C_g psi, gives every term of the group at once through its
+   diagonal form, here all of them from one pass per tile program.  Any
+   observable that is a linear combination of the terms then follows on the
+   host, e.g. at every step of a time series; observables outside H get a
+   plan of their own.  FP64 accumulation, fixed summation order.  state:
+   device pointer to 2^n amplitudes of `dtype`; out: host array of
+   sd_plan_info.n_terms doubles.  Synchronises `stream`.  Errors: SD_ERR_ARG,
+   SD_ERR_WORKSPACE (no workspace), SD_ERR_HIP. */
+sd_status sd_term_expectations(const sd_plan_t *p, const void *state, sd_dtype dtype,
+                               double *out, void *stream);
+
 /* FP64 reductions over 2^n amplitudes (device inputs, host outputs;
    synchronise `stream`).  sd_norm2: sum |a_x|^2.  sd_inner: sum conj(a_x) b_x
    written to out[0] (re), out[1] (im). */

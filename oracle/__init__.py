@@ -16,6 +16,7 @@ from .oracle import (  # noqa: F401
     evolve_terms_dense,
     apply_on_coset,
     energy,
+    term_expectations,
     fidelity,
     lib,
     build_lib,

@@ -278,6 +278,20 @@ def apply_on_coset(xs, zs, thetas, x0: int, span, amps) -> np.ndarray:
     return psi
 
 
+def term_expectations(n: int, paulis, coeffs, psi: np.ndarray, terms: Terms = None) -> np.ndarray:
+    """<psi|P_k|psi> of every merged term k (build_terms order), FP64, term by
+    term over the full state (no grouping)."""
+    t = terms if terms is not None else build_terms(n, paulis, coeffs)
+    psi = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    out = np.zeros(2)
+    vals = np.zeros(len(t.x))
+    L = lib()
+    for k in range(len(t.x)):
+        L.or_pauli_expect(n, _dp(psi.view(np.float64)), int(t.x[k]), int(t.z[k]), _dp(out))
+        vals[k] = out[0]
+    return vals
+
+
 def energy(n: int, paulis, coeffs, psi: np.ndarray, terms: Terms = None) -> float:
     t = terms if terms is not None else build_terms(n, paulis, coeffs)
     psi = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))

@@ -89,6 +89,7 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
         std::memcpy(t + o2, p.ztile.data(), 8 * (size_t)m);
         std::memcpy(t + o2 + 8 * m, p.coef.data(), 8 * (size_t)m);
+        std::memcpy(t + o2 + 16 * m, p.usign.data(), 8 * (size_t)m);
         toff += (term_bytes(m) + 255) / 256 * 256;
     }
 }
@@ -155,6 +156,10 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 constexpr int kBlock = 256;
 
 // MODE 0: evolve in place.  MODE 1: accumulate <psi|H_pass|psi> into partial[blockIdx].
+// MODE 2: <psi|P_k|psi> of every term k of the pass: the probabilities of the
+// transformed tile go through a full Walsh-Hadamard transform in LDS, whose
+// entry at term k's Lambda mask (times its sign) is the tile's share; thread
+// k keeps term k's running sum, written to partial[blockIdx * kMaxPassTerms + k].
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
@@ -171,6 +176,7 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
     const int64_t o2 = ((int64_t)m * 4 + 7) / 8 * 8;
     const uint64_t *ztile = (const uint64_t *)(tb + o2);
     const double *coef = (const double *)(tb + o2 + 8 * (int64_t)m);
+    const double *usgn = (const double *)(tb + o2 + 16 * (int64_t)m);
     const uint32_t rmask = (rho >= 32) ? ~0u : ((1u << rho) - 1);
     const uint64_t cmask = ((uint64_t)1 << c) - 1;
     const double scale = pd.scale;
@@ -181,7 +187,7 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
         for (int i = 0; i < pd.n_free; ++i)
             if ((ti >> i) & 1) xT |= (uint64_t)1 << pd.free_pos[i];
         for (int k = threadIdx.x; k < m; k += blockDim.x) {
-            const double v = coef[k];
+            const double v = MODE == 2 ? usgn[k] : coef[k];
             cks[k] = (__popcll(ztile[k] & xT) & 1) ? -v : v;
             zs[k] = zeta[k];
         }
@@ -227,7 +233,7 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
                     }
                 st_amp(state, (int64_t)(xT ^ off), tile[tc]);
             }
-        } else {
+        } else if (MODE == 1) {
             for (int64_t t = threadIdx.x; t < size; t += blockDim.x) {
                 double phi = 0.0;
                 for (int k = 0; k < m; ++k)
@@ -235,6 +241,14 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
                 const double2 a = tile[t];
                 acc += (a.x * a.x + a.y * a.y) * phi * scale;
             }
+        } else {
+            __syncthreads();
+            for (int64_t t = threadIdx.x; t < size; t += blockDim.x) {
+                const double2 a = tile[t];
+                tile[t] = make_double2((a.x * a.x + a.y * a.y) * scale, 0.0);
+            }
+            wht_lds(tile, D, D);
+            if ((int)threadIdx.x < m) acc += cks[threadIdx.x] * tile[zs[threadIdx.x] & (uint32_t)(size - 1)].x;
         }
         __syncthreads();
     }
@@ -242,6 +256,7 @@ k_pass(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
         double s = block_sum(acc, red);
         if (threadIdx.x == 0) partial[blockIdx.x] += s;
     }
+    if (MODE == 2 && (int)threadIdx.x < m) partial[(int64_t)blockIdx.x * kMaxPassTerms + threadIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,6 +1037,17 @@ k_inner(const T *__restrict__ a, const T *__restrict__ b, int64_t dim,
     }
 }
 
+// per-term totals of MODE 2: out[k] = sum over blocks b < count of
+// partial[b * kMaxPassTerms + k], in block order
+__global__ void k_term_final(const double *__restrict__ partial, int count, int m,
+                             double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    double s = 0.0;
+    for (int b = 0; b < count; ++b) s += partial[(int64_t)b * kMaxPassTerms + k];
+    out[k] = s;
+}
+
 // fixed-order final sum of `count` interleaved groups of `width` partials
 __global__ void k_final(const double *__restrict__ partial, int count, int width,
                         double *__restrict__ out) {
@@ -1279,6 +1305,56 @@ extern "C" sd_status sd_expectation(const sd_plan_t *p, const void *state, sd_dt
     r = hip_check(hipMemcpyAsync(energy, out, sizeof(double), hipMemcpyDeviceToHost, s), "copy energy");
     if (r != SD_OK) return r;
     return hip_check(hipStreamSynchronize(s), "sd_expectation sync");
+}
+
+extern "C" sd_status sd_term_expectations(const sd_plan_t *p, const void *state, sd_dtype dtype,
+                                          double *out, void *stream) {
+    if (!p || !state || !out) return fail(SD_ERR_ARG, "sd_term_expectations: null argument");
+    if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_term_expectations: bad dtype");
+    if (!p->bound) return fail(SD_ERR_WORKSPACE, "sd_term_expectations: no workspace bound");
+    std::call_once(g_once, init_device_props);
+    if (g_init_status != SD_OK) return fail(g_init_status, "device initialisation failed");
+    hipStream_t s = (hipStream_t)stream;
+    const uint8_t *ws = (const uint8_t *)p->ws;
+    double *partial = (double *)(ws + p->ws_off_terms);
+    double *res = partial + (int64_t)kTermGrid * kMaxPassTerms;
+    const Program &P = p->prog[dtype];
+    int64_t off = 0;
+    for (int i = 0; i < (int)P.passes.size(); ++i) {
+        const PassHost &ph = P.passes[i];
+        const int m = (int)ph.terms.size();
+        if (m == 0) continue;
+        if (ph.D > kMaxTileLog2 || m > kMaxPassTerms)
+            return fail(SD_ERR_INTERNAL, "pass exceeds the on-chip tile limits");
+        const PassDev *pd = (const PassDev *)(ws + p->ws_off_prog[dtype] + (int64_t)i * sizeof(PassDev));
+        const int grid = (int)std::min<int64_t>((int64_t)1 << (p->n - ph.D), kTermGrid);
+        const size_t lds = (size_t)16 << ph.D;
+        if (dtype == SD_C64)
+            hipLaunchKernelGGL((k_pass<float2, 2>), dim3(grid), dim3(kBlock), lds, s, (float2 *)state, pd,
+                               ws, 0.0, partial);
+        else
+            hipLaunchKernelGGL((k_pass<double2, 2>), dim3(grid), dim3(kBlock), lds, s, (double2 *)state,
+                               pd, ws, 0.0, partial);
+        sd_status r = hip_check(hipGetLastError(), "k_pass (terms) launch");
+        if (r != SD_OK) return r;
+        hipLaunchKernelGGL(k_term_final, dim3((m + 255) / 256), dim3(256), 0, s, partial, grid, m, res + off);
+        r = hip_check(hipGetLastError(), "term reduce");
+        if (r != SD_OK) return r;
+        off += m;
+    }
+    std::vector<double> host((size_t)off);
+    if (off) {
+        sd_status r = hip_check(hipMemcpyAsync(host.data(), res, (size_t)off * sizeof(double),
+                                               hipMemcpyDeviceToHost, s), "copy term values");
+        if (r != SD_OK) return r;
+    }
+    sd_status r = hip_check(hipStreamSynchronize(s), "sd_term_expectations sync");
+    if (r != SD_OK) return r;
+    for (size_t k = 0; k < p->terms.size(); ++k) out[k] = 0.0;
+    off = 0;
+    for (const PassHost &ph : P.passes)
+        for (size_t j = 0; j < ph.terms.size(); ++j) out[ph.terms[j]] = host[(size_t)off++];
+    return SD_OK;
 }
 
 namespace {

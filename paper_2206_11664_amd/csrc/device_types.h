@@ -6,6 +6,7 @@ namespace sd {
 
 constexpr int kMaxD = 16;            // tile dims a record can describe
 constexpr int kMaxPassTerms = 256;   // Lambda terms per pass (LDS budget)
+constexpr int kTermGrid = 256;       // blocks of a per-term expectation pass
 
 struct alignas(256) PassDev {
     int32_t n;          // qubits
@@ -49,10 +50,11 @@ struct alignas(256) PassDev {
                                     // a round 0 before Lambda's take a sign
 };
 
-// term arrays at term_off: uint32 zeta[m]; (pad to 8) uint64 ztile[m]; double coef[m]
+// term arrays at term_off: uint32 zeta[m]; (pad to 8) uint64 ztile[m]; double coef[m];
+// double usign[m] (coef without the Hamiltonian coefficient: +-1)
 inline int64_t term_bytes(int m) {
     int64_t a = ((int64_t)m * 4 + 7) / 8 * 8;
-    return a + (int64_t)m * 16;
+    return a + (int64_t)m * 24;
 }
 
 }  // namespace sd

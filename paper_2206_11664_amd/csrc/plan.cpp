@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "device_types.h"
 #include "sd_internal.h"
 
 using namespace sd;
@@ -119,6 +120,18 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
     off += (int64_t)(p->layer_data.size() * sizeof(uint64_t) + 255) / 256 * 256;
     p->ws_off_scratch = off;
     off += 64 * 1024;  // FP64 partial sums
+    // per-term expectations: per-block partials, then one value per pass term
+    p->ws_off_terms = off;
+    {
+        int64_t most = 0;
+        for (int d = 0; d < 2; ++d) {
+            int64_t t = 0;
+            for (auto &ps : p->prog[d].passes) t += (int64_t)ps.terms.size();
+            most = std::max(most, t);
+        }
+        off += ((int64_t)kTermGrid * kMaxPassTerms + most) * 8;
+        off = (off + 255) / 256 * 256;
+    }
     p->ws_needed = off;
     p->plan_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

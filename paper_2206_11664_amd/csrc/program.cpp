@@ -605,17 +605,19 @@ sd_status plan_rounds(PassHost *ps) {
     std::vector<int64_t> t2;
     std::vector<uint32_t> z2;
     std::vector<uint64_t> zt2;
-    std::vector<double> c2;
+    std::vector<double> c2, u2;
     for (size_t i : idx) {
         t2.push_back(p.terms[i]);
         z2.push_back(p.zeta[i]);
         zt2.push_back(p.ztile[i]);
         c2.push_back(p.coef[i]);
+        u2.push_back(p.usign[i]);
     }
     p.terms.swap(t2);
     p.zeta.swap(z2);
     p.ztile.swap(zt2);
     p.coef.swap(c2);
+    p.usign.swap(u2);
     p.bucket.assign(33, 0);
     for (size_t i = 0; i < m; ++i) p.bucket[pattern(p.zeta[i]) + 1]++;
     for (int w = 0; w < 32; ++w) p.bucket[w + 1] += p.bucket[w];
@@ -757,6 +759,7 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
     p.zeta.clear();
     p.ztile.clear();
     p.coef.clear();
+    p.usign.clear();
     p.terms = vterm;
     for (size_t i = 0; i < vterm.size(); ++i) {
         const int64_t k = vterm[i];
@@ -764,6 +767,7 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
         p.ztile.push_back(T[k].z);
         double s = (sr.sign[i] ? -1.0 : 1.0) * (ephase[i] == 2 ? -1.0 : 1.0);
         p.coef.push_back(T[k].c * s);
+        p.usign.push_back(s);
     }
     sd_status st = canonicalize(&p);
     if (st != SD_OK) return st;

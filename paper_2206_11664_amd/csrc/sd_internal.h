@@ -127,6 +127,7 @@ struct PassHost {
     std::vector<uint32_t> zeta;     // per term, D-bit mask of Lambda
     std::vector<uint64_t> ztile;    // per term, physical z for the tile sign
     std::vector<double> coef;       // per term, c_k (-1)^{r_k} i^{e_k}
+    std::vector<double> usign;      // per term, (-1)^{r_k} i^{e_k} (+-1): coef without c_k
     double coef_abs_sum = 0;        // sum |c_k| (bounds the phase angle)
     // register-round schedule of the on-chip Walsh-Hadamard (see device.hip)
     int nr = 0;                     // chunks of <= kChunkBits span coordinates
@@ -203,6 +204,7 @@ struct sd_plan_s {
     int64_t ws_needed = 0;
     int64_t ws_off_prog[2] = {0, 0};   // byte offsets of packed pass tables
     int64_t ws_off_scratch = 0;        // reduction scratch
+    int64_t ws_off_terms = 0;          // per-term expectations: partials, then results
     bool bound = false;
     // layer-by-layer and term-by-term execution
     int32_t mode = SD_MODE_TILES;

@@ -29,7 +29,7 @@ EXPORTED = [
     "sd_hamiltonian_destroy", "sd_plan_options_default", "sd_plan", "sd_plan_info_get",
     "sd_plan_export_group", "sd_plan_pass_count", "sd_plan_export_pass", "sd_plan_export_rounds",
     "sd_plan_destroy",
-    "sd_bind_workspace", "sd_evolve", "sd_expectation", "sd_norm2", "sd_inner",
+    "sd_bind_workspace", "sd_evolve", "sd_expectation", "sd_term_expectations", "sd_norm2", "sd_inner",
     "sd_ensemble_create", "sd_ensemble_workspace_bytes", "sd_ensemble_bind_workspace",
     "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_status_string",
     "sd_last_error", "sd_version",
@@ -123,6 +123,7 @@ def lib():
         "sd_bind_workspace": (st, [vp, vp, ctypes.c_size_t, vp]),
         "sd_evolve": (st, [vp, vp, ctypes.c_int, ctypes.c_double, i64, i32, vp]),
         "sd_expectation": (st, [vp, vp, ctypes.c_int, dp, vp]),
+        "sd_term_expectations": (st, [vp, vp, ctypes.c_int, dp, vp]),
         "sd_norm2": (st, [vp, ctypes.c_int, i32, dp, vp]),
         "sd_inner": (st, [vp, vp, ctypes.c_int, i32, dp, vp]),
         "sd_ensemble_create": (st, [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.POINTER(vp)]),
@@ -329,6 +330,16 @@ def sd_expectation(p: int, state, stream=None) -> float:
     return e.value
 
 
+def sd_term_expectations(p: int, state, stream=None) -> np.ndarray:
+    """<psi|P_k|psi> for every merged term k of the plan (sd_hamiltonian_terms order)."""
+    info = sd_plan_info_get(p)
+    out = np.zeros(int(info.n_terms), dtype=np.float64)
+    _check(lib().sd_term_expectations(p, _dev_ptr(state), _dtype_of(state),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _stream(stream)))
+    return out
+
+
 def sd_norm2(state, n_qubits: int, stream=None) -> float:
     out = ctypes.c_double()
     _check(lib().sd_norm2(_dev_ptr(state), _dtype_of(state), n_qubits, ctypes.byref(out),
@@ -408,6 +419,9 @@ class Plan:
 
     def expectation(self, state, stream=None) -> float:
         return sd_expectation(self.p, state, stream)
+
+    def term_expectations(self, state, stream=None) -> np.ndarray:
+        return sd_term_expectations(self.p, state, stream)
 
     def group(self, g: int) -> GroupExport:
         return sd_plan_export_group(self.p, g)

@@ -484,3 +484,49 @@ def test_syk_majorana_modes(n, mode, dtype):
     # many small groups): every execution mode against the oracle
     m = workloads.syk_majorana(n)
     check(m, dtype, m.dt, 2, 1, dict(mode=mode), psi0=m.initial_state())
+
+
+@pytest.mark.parametrize("case", ["klocal", "tfim", "syk", "jw", "wide"])
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_term_expectations_match_oracle(case, dtype):
+    # grouped measurement: <psi|P_k|psi> of every term from one transform per
+    # (sub-)group, against the oracle term by term; their weighted sum is the
+    # energy of sd_expectation
+    m, opts = {
+        "klocal": (workloads.random_klocal(n=12, m=150, seed=41, init_seed=42), {}),
+        "tfim": (workloads.tfim_fully_connected(10), {}),
+        "syk": (workloads.syk_majorana(6), {}),
+        "jw": (workloads.jw_fermionic(n=11, total=150), dict(tile_log2_c64=10, tile_log2_c128=10)),
+        "wide": (workloads.random_klocal(n=16, m=300, seed=43, init_seed=44), {}),
+    }[case]
+    o = sd.sd_plan_options_default()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs, o).bind()
+    psi = workloads.random_state(m.n, 45)
+    d = torch.from_numpy(psi).to(TDT[dtype]).cuda()
+    got = plan.term_expectations(d)
+    ref_state = d.cpu().numpy().astype(np.complex128)
+    want = oracle.term_expectations(m.n, m.paulis, m.coeffs, ref_state)
+    t = oracle.build_terms(m.n, m.paulis, m.coeffs)
+    err = float(np.abs(got - want).max())
+    print(f"[gpu] term expectations {case} dtype={dtype} terms={len(want)} max err {err:.2e}", flush=True)
+    assert err <= (1e-12 if dtype == sd.SD_C128 else 1e-6)
+    assert abs(float(np.dot(t.c, got)) - plan.expectation(d)) <= 1e-9
+
+
+def test_term_expectations_time_series():
+    # observables along a trajectory: after every step of an XXZ chain the
+    # bond and field terms of H, from the evolving GPU state, against the
+    # oracle's state
+    m = workloads.xxz_chain(n=12, steps=5)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    psi = m.initial_state()
+    d = torch.from_numpy(psi).cuda()
+    t = oracle.build_terms(m.n, m.paulis, m.coeffs)
+    for step in range(5):
+        plan.evolve(d, 0.05, 1, 2)
+        psi = oracle.evolve(m.n, m.paulis, m.coeffs, psi, 0.05, 1, 2, terms=t)
+        got = plan.term_expectations(d)
+        want = oracle.term_expectations(m.n, m.paulis, m.coeffs, psi, terms=t)
+        assert np.abs(got - want).max() <= 1e-12, step
