@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
-    ap.add_argument("--cpu-sample-terms", type=int, default=16)
+    ap.add_argument("--cpu-sample-terms", type=int, default=320)
     ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep"], default=None,
                     help="instead of the benchmark line: the paper's fully connected TFIM "
                          "or SYK Majorana sweep, grouped vs term by term (one JSON line per n)")

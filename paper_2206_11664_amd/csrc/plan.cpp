@@ -101,10 +101,10 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
     build_layers(*p);
 
     sd_status st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c64,
-                                   opt.coalesce_log2_c64, &p->prog[SD_C64]);
+                                   opt.coalesce_log2_c64, &p->prog[SD_C64], true);
     if (st == SD_OK)
         st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c128,
-                             opt.coalesce_log2_c128, &p->prog[SD_C128]);
+                             opt.coalesce_log2_c128, &p->prog[SD_C128], false);
     if (st != SD_OK) {
         delete p;
         return st;

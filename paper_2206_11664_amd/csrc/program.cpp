@@ -778,7 +778,7 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
 
 sd_status compile_program(int n, const std::vector<Term> &T,
                           const std::vector<std::vector<int64_t>> &groups,
-                          int D_max, int c, Program *out) {
+                          int D_max, int c, Program *out, bool shrink) {
     Program &P = *out;
     P.D_max = D_max;
     P.c = c;
@@ -879,7 +879,16 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         std::vector<std::vector<int64_t>> &subs = best_split.first;
         for (auto &s : subs) {
             PassHost ps;
-            sd_status st = build_pass(n, T, (int32_t)g, s, Dcap, cc, &ps);
+            // shrink: the smallest tile (not below the register-round minimum)
+            // that holds the sub-group's span and low bits
+            int Dt = Dcap;
+            if (shrink) {
+                Echelon sp;
+                for (int q = 0; q < cc; ++q) sp.insert(1ull << q);
+                for (int64_t k : s) sp.insert(T[k].x);
+                Dt = std::min(Dcap, std::max(sp.dim(), 2 * kRegBits + kXBits));
+            }
+            sd_status st = build_pass(n, T, (int32_t)g, s, Dt, cc, &ps);
             if (st != SD_OK) return st;
             P.passes.push_back(std::move(ps));
         }

@@ -180,9 +180,12 @@ struct Program {
     std::vector<int32_t> group_first;    // first pass of group g (K+1 entries)
 };
 
+// shrink: give each pass the smallest tile (down to 2^10) that holds it, so
+// that small passes run several blocks per CU (complex64 runs faster so;
+// complex128 keeps D_max)
 sd_status compile_program(int n, const std::vector<Term> &terms,
                           const std::vector<std::vector<int64_t>> &groups,
-                          int D_max, int c, Program *out);
+                          int D_max, int c, Program *out, bool shrink);
 
 // bytes of the packed device records of a program (device.hip)
 int64_t pack_size(const Program &P);
