@@ -238,6 +238,10 @@ typedef struct {
                                   view) and round 0 reads it from LDS; used when
                                   the lowest address bits cannot be round 0's
                                   leading lanes                                */
+    uint32_t czmask[4];        /* round r: bit g = 1 if register pattern g takes
+                                  a sign from the CZ between the chunk's register
+                                  slots (before a forward round's butterflies,
+                                  after a backward round's)                    */
     int32_t shift0;            /* 1: round 0's leading lanes (the low address
                                   bits) have components along round 0's own
                                   coordinates; lanes_post[0] holds them without

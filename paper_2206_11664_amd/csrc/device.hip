@@ -70,6 +70,7 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
             d.iflag[r] = p.iflag[r];
             d.dflag[r] = p.dflag[r];
             d.later[r] = p.later[r];
+            d.czm[r] = p.czm[r];
             for (size_t i = 0; i < p.lanes[r].size() && i < (size_t)kMaxD; ++i) {
                 d.lanes[r][i] = p.lanes[r][i];
                 d.lanes_post[r][i] = p.lanes_post[r][i];
@@ -580,12 +581,26 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     // register g; it is kept in the thread's round-0 read address, which a
     // direct pass never uses (round 0 reads HBM forward, its write layout
     // backward).
-    uint32_t sgn0 = 0;
+    // A CZ or S among round 0's register coordinates makes the shift also
+    // move the outputs, by m0(t) = M d(t) (M: the CZ/S form on those
+    // coordinates; added to the round's output layout and, in a single
+    // round, to Lambda's sign coordinates), and adds the constant
+    // (-1)^{Q(d)} (Q: the CZ pairs), folded into the sign.
+    uint32_t sgn0 = 0, m0 = 0;
     if (pd.shift0 && !staged) {
         uint32_t d = 0;
         for (int i = 0; i < kLE && i < TL; ++i)
             if ((tid >> i) & 1) d ^= pd.lanes[0][i] ^ pd.lanes_post[0][i];
-        uint32_t w = 0, kap = 0;
+        const int nb0 = __popc(pd.bmask[0]);
+        uint32_t regm = 0, qd = 0;
+        for (int l = 0; l < nb0; ++l) regm |= 1u << pd.reg[0][l];
+        for (int l = 0; l < nb0; ++l) {
+            const int a = pd.reg[0][l];
+            m0 |= (uint32_t)(__popc(pd.B[a] & regm & d) & 1) << a;
+            const uint32_t higher = regm & ~((2u << a) - 1u);
+            qd ^= (d >> a) & (uint32_t)__popc(pd.B[a] & higher & d);
+        }
+        uint32_t w = 0, kap = qd & 1u;
         for (int l = 0; l < kLE; ++l) w |= ((d >> pd.regpost[0][l]) & 1u) << l;
         for (int x = 0; x < pd.nx[0]; ++x) kap ^= (tid >> (kLE + x)) & (d >> pd.reg[0][2 + x]) & 1u;
         for (int g = 0; g < kE; ++g) sgn0 |= ((__popc(g & w) ^ kap) & 1u) << g;
@@ -601,6 +616,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                 bt ^= pd.lanes[r][i];
                 btp ^= pd.lanes_post[r][i];
             }
+        if (r == 0) btp ^= m0;
         uint32_t pm = 0;
         for (int l = 0; l < kLE + 2; ++l) {
             int a = -1;
@@ -752,6 +768,18 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             im[g] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(im[g]) ^ mm));
         }
     };
+    // the CZ between register slots of a round's chunk: a sign per register
+    // pattern (bit g of czm), the same for every thread; in place on the
+    // high words, before a forward round's butterflies and after a backward
+    // round's
+    auto apply_cz = [&](uint32_t czm) {
+#pragma unroll
+        for (int g = 0; g < kE; ++g) {
+            const uint64_t mm = (uint64_t)(((czm >> g) & 1u) << 31) << 32;
+            re[g] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(re[g]) ^ mm));
+            im[g] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(im[g]) ^ mm));
+        }
+    };
     // exchange of register bits 2, 3 with lane bits 4, 5 (nx of them), and
     // butterflies on register bits 2, 3 (nx of them)
     auto xchg = [&](int nx) {
@@ -793,9 +821,11 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             }
             const int nb = __popc(pd.bmask[r]);
             const int nx = pd.nx[r];
+            const uint32_t czm = pd.czm[r];
             if (step > 0 || staged) read16(ra, rin);  // (step 0 of a direct pass: in re/im)
             if (!lam) {
                 if (sh0 && last) apply_sign0(ab.x);
+                if (fwd && czm) apply_cz(czm);
                 bfly_fwd<0, false>(re, im);
                 if (GEN) {
                     plain_rest(nb);
@@ -810,12 +840,14 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                     bfly_fwd<2, false>(re, im);
                     bfly_fwd<3, false>(re, im);
                 }
+                if (!fwd && czm) apply_cz(czm);
                 if (sh0 && step == 0) apply_sign0(ab.x);
                 if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
                 __syncthreads();
                 continue;
             }
             const bool tw = pd.iflag[r] & 1u;
+            if (czm) apply_cz(czm);
             if (nb > 0) {
                 if (tw) bfly_fwd<0, true>(re, im);
                 else bfly_fwd<0, false>(re, im);
@@ -887,6 +919,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
                 if (tw) bfly_bwd<0, true>(re, im);
                 else bfly_bwd<0, false>(re, im);
             }
+            if (czm) apply_cz(czm);
             if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
             __syncthreads();
         }

@@ -44,6 +44,8 @@ struct alignas(256) PassDev {
     uint32_t swz[4];                // LDS slot of t: t ^ sum_j parity(t & swz[j]) << j
     int32_t staged;                 // round 0 reads the tile from LDS, staged in
                                     // pivot order (u_hi, mr), not from HBM
+    uint32_t czm[4];                // round r: bit g = sign of register pattern g
+                                    // (CZ between the chunk's register slots)
     int32_t shift0;                 // round 0's lanes 0..3 (lanes) have components
                                     // along its own coordinates, which its LDS
                                     // layout (lanes_post) drops: the outputs of

@@ -235,6 +235,7 @@ extern "C" sd_status sd_plan_export_rounds(const sd_plan_t *p, sd_dtype dt, int3
     for (int j = 0; j < 4; ++j) v->swz[j] = h.swz[j];
     v->staged = h.staged ? 1 : 0;
     v->shift0 = h.shift0 ? 1 : 0;
+    for (int r = 0; r < 4; ++r) v->czmask[r] = h.czm[r];
     return SD_OK;
 }
 

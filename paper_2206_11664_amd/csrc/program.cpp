@@ -178,10 +178,11 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<
                 if ((co >> i) & 1) dirty[i] = 1;
         }
     }
-    // Assign the vectors to K chunks of at most kChunkBits each, no two
-    // vectors of one chunk with a nonzero product (a CZ inside a round is
-    // not supported), the odd vector first in the last chunk (the Lambda
-    // round: its S is the pass's only i twiddle).  Round 0's chunk decides
+    // Assign the vectors to K chunks of at most kChunkBits each; vectors of
+    // one chunk with a nonzero product (a CZ inside the round) are allowed
+    // among at most kRegBits of them, which take the register slots (there
+    // the CZ is a sign per register pattern); the odd vector goes first in
+    // the last chunk (the Lambda round: its S is the pass's only i twiddle).  Round 0's chunk decides
     // how the tile moves between HBM and registers: made of clean vectors
     // only, the low address bits are plain lanes of round 0; meeting low0 in
     // zero alone, they are lanes with a sign correction (shift0); otherwise
@@ -223,7 +224,7 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<
             if (((mem0 >> i) & 1) && !e.insert(all[i])) return true;
         return false;
     };
-    auto search = [&](int K, int mode, const std::vector<int> &cap) -> bool {
+    auto search = [&](int K, int mode, bool inner_cz, const std::vector<int> &cap) -> bool {
         std::vector<int> size(K, 0);
         std::vector<uint32_t> mem(K, 0);
         int budget = 200000;  // node limit (never reached at these sizes)
@@ -240,7 +241,17 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<
             if (room < left) return false;
             for (int r = 0; r < K; ++r) {
                 if (v == io && r != K - 1) continue;
-                if (size[r] >= cap[r] || (mem[r] & conf[v])) continue;
+                if (size[r] >= cap[r]) continue;
+                if (mem[r] & conf[v]) {
+                    if (!inner_cz) continue;
+                    uint32_t inv = 0;
+                    const uint32_t mm = mem[r] | (1u << v);
+                    for (int i = 0; i < nv; ++i)
+                        if (((mm >> i) & 1) && (conf[i] & mm)) inv |= 1u << i;
+                    // (the odd vector takes register slot 0 of the last chunk)
+                    if (io >= 0 && r == K - 1) inv |= 1u << io;
+                    if (__builtin_popcount(inv) > kRegBits) continue;
+                }
                 if (mode == 0 && r == 0 && dirty[v]) continue;
                 if (mode == 1 && r == 0 && meets_low0(mem[0] | (1u << v))) continue;
                 size[r]++;
@@ -258,16 +269,21 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<
     std::vector<std::vector<uint32_t>> ch;
     int bestK = 0;
     const int kmin = std::max(1, (nv + kChunkBits - 1) / kChunkBits);
+    // Order of preference at a chunk count: clean round 0 without a CZ
+    // inside a chunk (no sign work), clean with it (a sign mask per such
+    // round), shifted round 0 (per-thread sign) without and with, staged.
     for (int K = kmin; K <= 4 && !bestK; ++K) {
-        for (int mode = 0; mode < 3 && !bestK; ++mode) {
+        for (int step = 0; step < 6 && !bestK; ++step) {
+            const int mode = step / 2;
+            const bool inner_cz = step & 1;
             // (a single round is Lambda's: no sign correction there, only the
             // layout, so "meets low0 in zero" suffices for it as well)
             // first with the chunks before the last full, then any sizes
             std::vector<int> exact(K, kChunkBits);
             exact[K - 1] = nv - kChunkBits * (K - 1);
             std::vector<int> loose(K, kChunkBits);
-            if (exact[K - 1] >= 1 && search(K, mode, exact)) bestK = K;
-            else if (search(K, mode, loose)) bestK = K;
+            if (exact[K - 1] >= 1 && search(K, mode, inner_cz, exact)) bestK = K;
+            else if (search(K, mode, inner_cz, loose)) bestK = K;
         }
     }
     if (!bestK) {
@@ -275,10 +291,18 @@ void canonical_basis(const std::vector<uint32_t> &B, int rho, const std::vector<
         ch.assign(1, {});
         for (int i = 0; i < nv; ++i) ch[0].push_back(all[i]);
     } else {
+        // within a chunk: the odd vector, then the vectors with a partner in
+        // the chunk (register slots), then the rest
         ch.assign(bestK, {});
+        std::vector<uint32_t> cmem(bestK, 0);
+        for (int i = 0; i < nv; ++i) cmem[asg[i]] |= 1u << i;
         if (io >= 0) ch[bestK - 1].push_back(all[io]);
-        for (int i = 0; i < nv; ++i)
-            if (i != io) ch[asg[i]].push_back(all[i]);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < nv; ++i) {
+                if (i == io) continue;
+                const bool inner = (conf[i] & cmem[asg[i]]) != 0;
+                if (inner == (pass == 0)) ch[asg[i]].push_back(all[i]);
+            }
     }
     f->clear();
     chunks->clear();
@@ -341,12 +365,14 @@ sd_status canonicalize(PassHost *ps) {
         for (int b = 0; b < rho; ++b)
             if (b != a && bil(p.B, f[a], f[b])) Bn[a] |= 1u << b;
     }
-    // every chunk must be free of CZ inside it
+    // a CZ inside a chunk only between its register slots (its first
+    // kRegBits coordinates)
     int off = 0;
     for (int s : p.chunk) {
         const uint32_t cm = ((1u << s) - 1) << off;
         for (int a = off; a < off + s; ++a)
-            if (Bn[a] & cm & ~(1u << a)) return fail(SD_ERR_INTERNAL, "CZ inside a register chunk");
+            if (a - off >= kRegBits && (Bn[a] & cm & ~(1u << a)))
+                return fail(SD_ERR_INTERNAL, "CZ inside a chunk outside its register slots");
         off += s;
     }
     for (uint32_t &z : p.zeta)
@@ -406,7 +432,7 @@ sd_status plan_rounds(PassHost *ps) {
     p.nr = 0;
     p.full_rounds = true;
     for (int r = 0; r < 4; ++r) {
-        p.bmask[r] = p.iflag[r] = p.dflag[r] = p.later[r] = 0;
+        p.bmask[r] = p.iflag[r] = p.dflag[r] = p.later[r] = p.czm[r] = 0;
         p.nx[r] = 0;
         p.lanes[r].clear();
         p.lanes_post[r].clear();
@@ -464,6 +490,13 @@ sd_status plan_rounds(PassHost *ps) {
             if ((p.B[a] >> a) & 1) p.iflag[r] |= 1u << l;
             if ((p.zq >> a) & 1) p.dflag[r] |= 1u << l;
         }
+        // CZ between register slots of the chunk: sign of register pattern g
+        // is the parity of the CZ pairs that g has both bits of
+        for (int l1 = 0; l1 < std::min(s, RB); ++l1)
+            for (int l2 = l1 + 1; l2 < std::min(s, RB); ++l2)
+                if ((p.B[off + l1] >> (off + l2)) & 1)
+                    for (int g = 0; g < (1 << RB); ++g)
+                        if ((g >> l1) & (g >> l2) & 1) p.czm[r] ^= 1u << g;
         off += s;
     }
     p.lam_round = nrounds - 1;

@@ -141,6 +141,8 @@ struct PassHost {
     uint32_t iflag[4] = {};         // register slots whose coordinate has an S
     uint32_t dflag[4] = {};         // chunk slots (0..3 registers, 4..5 lanes) with a Z
     uint32_t later[4] = {};         // span coordinates of the chunks after r
+    uint32_t czm[4] = {};           // bit g: sign of register pattern g from the
+                                    // CZ between register slots of chunk r
     int lam_round = 0;              // chunk whose round applies Lambda
     bool full_rounds = true;        // every chunk before lam_round is full
     // lane bit i of a thread is tile coordinate vector lanes[r][i] in round r

@@ -88,7 +88,7 @@ class sd_round_view(ctypes.Structure):
                 ("lanes", ctypes.POINTER(ctypes.c_uint32) * 4),
                 ("lanes_post", ctypes.POINTER(ctypes.c_uint32) * 4),
                 ("swz", ctypes.c_uint32 * 4), ("staged", ctypes.c_int32),
-                ("shift0", ctypes.c_int32)]
+                ("czmask", ctypes.c_uint32 * 4), ("shift0", ctypes.c_int32)]
 
 
 _lib = None
@@ -302,7 +302,8 @@ def sd_plan_export_rounds(p: int, dtype: int, i: int) -> dict:
                       for r in range(4)],
             "lanes_post": [[v.lanes_post[r][i] for i in range(v.n_lanes)]
                            if r < nrounds and v.n_lanes else [] for r in range(4)],
-            "swz": list(v.swz), "staged": v.staged, "shift0": v.shift0}
+            "swz": list(v.swz), "staged": v.staged, "shift0": v.shift0,
+            "czmask": list(v.czmask)}
 
 
 def sd_plan_destroy(p: int):

@@ -136,6 +136,36 @@ def apply_pass(psi, n, ps, rv, tau):
                 y0[:, g] ^= 1 << rv["reg"][0][b]
     assert sorted(y0.ravel().tolist()) == list(range(1 << D))
     off = phys(y0)
+    # round 0 with low-bit lanes that have components d(t) along its own
+    # coordinates: its outputs are laid out without them (lanes_post[0]) and,
+    # when it is not Lambda's round, carry the sign (-1)^{k.d(t)}
+    # With a CZ or S among round 0's register coordinates the shift also
+    # moves the outputs by m0(t) = M d(t) (M: the CZ/S form on those
+    # coordinates) and adds the constant (-1)^{Q(d)}.
+    sign0 = None
+    m0 = np.zeros(T, dtype=np.int64)
+    if rv.get("shift0", 0) and not staged:
+        d = np.zeros(T, dtype=np.int64)
+        for i in range(min(4, TL)):
+            d ^= ((tid >> i) & 1) * (rv["lanes"][0][i] ^ rv["lanes_post"][0][i])
+        nb0 = bin(rv["bmask"][0]).count("1")
+        regm = sum(1 << rv["reg"][0][l] for l in range(nb0))
+        qd = np.zeros(T, dtype=np.int64)
+        for l in range(nb0):
+            a = rv["reg"][0][l]
+            m0 |= (_popc(B[a] & regm & d) & 1) << a
+            higher = regm & ~((2 << a) - 1)
+            qd ^= ((d >> a) & 1) & _popc(B[a] & higher & d)
+        w = np.zeros(T, dtype=np.int64)
+        for l in range(4):
+            w |= ((d >> rv["regpost"][0][l]) & 1) << l
+        kap = qd & 1
+        for x in range(rv["nx"][0]):
+            kap ^= (tid >> (4 + x)) & (d >> rv["reg"][0][2 + x]) & 1
+        if nr >= 2:
+            sign0 = np.ones((T, 16))
+            for g in range(16):
+                sign0[:, g] = np.where((_popc(g & w) ^ kap) & 1, -1.0, 1.0)
     # per-thread round addresses
     rd = np.zeros((nrounds, T), dtype=np.int64)
     wr = np.zeros((nrounds, T), dtype=np.int64)
@@ -155,29 +185,14 @@ def apply_pass(psi, n, ps, rv, tau):
                 continue
             bit = (_popc(B[a] & rv["later"][r] & bt) ^ (rv["dflag"][r] >> l)) & 1
             pm |= bit << a
+        if r == 0:
+            btp = btp ^ m0
         rd[r] = lds_slot(bt, swz)
         if r == nrounds - 1:
             sgnb = btp ^ pm
             wr[r] = rd[r]
         else:
             wr[r] = lds_slot(btp ^ pm, swz)
-    # round 0 with low-bit lanes that have components d(t) along its own
-    # coordinates: its outputs are laid out without them (lanes_post[0]) and,
-    # when it is not Lambda's round, carry the sign (-1)^{k.d(t)}
-    sign0 = None
-    if rv.get("shift0", 0) and not staged and nr >= 2:
-        d = np.zeros(T, dtype=np.int64)
-        for i in range(min(4, TL)):
-            d ^= ((tid >> i) & 1) * (rv["lanes"][0][i] ^ rv["lanes_post"][0][i])
-        w = np.zeros(T, dtype=np.int64)
-        for l in range(4):
-            w |= ((d >> rv["regpost"][0][l]) & 1) << l
-        kap = np.zeros(T, dtype=np.int64)
-        for x in range(rv["nx"][0]):
-            kap ^= (tid >> (4 + x)) & (d >> rv["reg"][0][2 + x]) & 1
-        sign0 = np.ones((T, 16))
-        for g in range(16):
-            sign0[:, g] = np.where((_popc(g & w) ^ kap) & 1, -1.0, 1.0)
     rs_pre = [[int(lds_slot(1 << rv["reg"][r][b], swz)) for b in range(4)] for r in range(4)]
     rs_post = [[int(lds_slot(1 << rv["regpost"][r][b], swz)) for b in range(4)] for r in range(4)]
     bucket = rv["bucket"]
@@ -220,16 +235,23 @@ def apply_pass(psi, n, ps, rv, tau):
             nb = bin(rv["bmask"][r]).count("1")
             nx = rv["nx"][r]
             tw = rv["iflag"][r] & 1
+            czm = rv.get("czmask", [0, 0, 0, 0])[r]
+            czs = np.array([-1.0 if (czm >> g) & 1 else 1.0 for g in range(16)])
             if not lam:
                 if sign0 is not None and r == 0 and last:
                     R = R * sign0
+                if fwd:
+                    R = R * czs
                 for L in range(nb):
                     _stage(R, L, 0, True)
                 _xchg(R, nx)
                 _stages_x(R, nx)
+                if not fwd:
+                    R = R * czs
                 if sign0 is not None and r == 0 and step == 0:
                     R = R * sign0
             else:
+                R = R * czs
                 if nb:
                     _stage(R, 0, tw, True)
                     for L in range(1, nb):
@@ -254,6 +276,7 @@ def apply_pass(psi, n, ps, rv, tau):
                     for L in range(1, nb):
                         _stage(R, L, 0, False)
                     _stage(R, 0, tw, False)
+                R = R * czs
             if last and not staged:
                 out[xT ^ off] = R
             else:

@@ -530,3 +530,12 @@ def test_term_expectations_time_series():
         got = plan.term_expectations(d)
         want = oracle.term_expectations(m.n, m.paulis, m.coeffs, psi, terms=t)
         assert np.abs(got - want).max() <= 1e-12, step
+
+
+@pytest.mark.parametrize("n,seed,m,D,dtype", [(12, 3, 300, 10, sd.SD_C64), (12, 19, 150, 10, sd.SD_C128),
+                                              (14, 14, 300, 13, sd.SD_C64)])
+def test_shifted_round0_with_cz(n, seed, m, D, dtype):
+    # plans with a shifted round 0 whose chunk holds a CZ between register
+    # slots (its outputs move by M d(t) as well as taking the sign)
+    w = workloads.random_klocal(n=n, m=m, seed=seed, init_seed=2)
+    check(w, dtype, 0.11, 3, 2, dict(tile_log2_c64=D, tile_log2_c128=D))

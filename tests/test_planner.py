@@ -324,7 +324,8 @@ def _export_all(p, dtype):
 
 def _check_round_structure(ps, rv):
     """Chunks hold consecutive span coordinates (register slots first, then
-    the exchanged lane coordinates) and no CZ inside a chunk; fillers are never
+    the exchanged lane coordinates), a CZ inside a chunk only between its
+    register slots (exported as the round's sign mask); fillers are never
     span coordinates of a later chunk; the only S sits in register slot 0 of
     the Lambda round; round 0's leading lanes are the lowest address bits."""
     rho, B = ps["rho"], [int(v) for v in ps["cz_s"]]
@@ -343,8 +344,18 @@ def _check_round_structure(ps, rv):
         assert coords == list(range(len(seen), len(seen) + nb + nx))
         seen += coords
         cm = sum(1 << a for a in coords)
+        regs = coords[:4]
+        czm = 0
+        for l1 in range(len(regs)):
+            for l2 in range(l1 + 1, len(regs)):
+                if (B[regs[l1]] >> regs[l2]) & 1:
+                    for g in range(16):
+                        if (g >> l1) & (g >> l2) & 1:
+                            czm ^= 1 << g
+        assert rv["czmask"][r] == czm
         for l, a in enumerate(coords):
-            assert B[a] & cm & ~(1 << a) == 0, "CZ inside a register chunk"
+            if l >= 4:
+                assert B[a] & cm & ~(1 << a) == 0, "CZ inside a chunk outside its register slots"
             assert ((rv["iflag"][r] >> l) & 1) == ((B[a] >> a) & 1)
             assert ((rv["dflag"][r] >> l) & 1) == ((ps["z_sign"] >> a) & 1)
             if (B[a] >> a) & 1:
@@ -432,10 +443,13 @@ def test_register_rounds_models_match_oracle(case, dtype):
     passes, rounds = _export_all(p, dtype)
     for q, r in zip(passes, rounds):
         _check_round_structure(q, r)
-    if case in ("klocal", "wide", "n16"):
-        # these plans include passes whose round-0 lanes are shifted (direct
-        # I/O with the layout and sign correction)
+    if case == "n16":
+        # passes whose round-0 lanes are shifted (direct I/O with the layout
+        # and sign correction)
         assert any(r["shift0"] and not r["staged"] and r["n_rounds"] >= 2 for r in rounds)
+    if case in ("klocal", "jw", "wide", "n16"):
+        # rounds with a CZ between register slots of their chunk
+        assert any(any(r["czmask"]) for r in rounds)
     psi0 = workloads.random_state(m.n, 3)
     got = round_emulator.evolve(psi0, m.n, passes, rounds, info.n_groups, 0.11, 1, 2)
     want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0, 0.11, 1, 2)
@@ -455,3 +469,24 @@ def test_register_round_structure_full_size(which):
             if q["tile_log2"] >= 10:
                 _check_round_structure(q, r)
 
+
+
+# plans with a shifted round 0 whose chunk also holds a CZ between register
+# slots (the shift then also moves round 0's outputs, by M d(t))
+SHIFT_CZ_CASES = [(12, 3, 300, 10, sd.SD_C64), (12, 19, 150, 10, sd.SD_C128),
+                  (14, 14, 300, 13, sd.SD_C64)]
+
+
+@pytest.mark.parametrize("n,seed,m,D,dtype", SHIFT_CZ_CASES)
+def test_register_rounds_shift_with_cz_matches_oracle(n, seed, m, D, dtype):
+    w = workloads.random_klocal(n=n, m=m, seed=seed, init_seed=2)
+    h, p = plan_for(w.n, w.paulis, w.coeffs, tile_log2_c64=D, tile_log2_c128=D)
+    info = sd.sd_plan_info_get(p)
+    passes, rounds = _export_all(p, dtype)
+    for q, r in zip(passes, rounds):
+        _check_round_structure(q, r)
+    assert any(r["shift0"] and not r["staged"] and r["czmask"][0] for r in rounds)
+    psi0 = workloads.random_state(w.n, 3)
+    got = round_emulator.evolve(psi0, w.n, passes, rounds, info.n_groups, 0.11, 1, 2)
+    want = oracle.evolve(w.n, w.paulis, w.coeffs, psi0, 0.11, 1, 2)
+    assert np.abs(got - want).max() < 1e-13
