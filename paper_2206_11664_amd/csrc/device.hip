@@ -864,11 +864,14 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
 #pragma unroll
             for (int w = 0; w < kE; ++w) {
                 double sacc = 0.0;
-#pragma unroll 2
+                // the sign bit of the coefficient flipped by the parity of
+                // the term's mask on the thread's coordinates
+#pragma unroll 4
                 for (int k = bk[w]; k < bk[w + 1]; ++k) {
                     const double2 rec = trec[k];
                     const uint32_t z = (uint32_t)__double_as_longlong(rec.y);
-                    sacc += (__popc(z & sgnb) & 1) ? -rec.x : rec.x;
+                    const uint64_t flip = (uint64_t)__popc(z & sgnb) << 63;
+                    sacc += __longlong_as_double((long long)((uint64_t)__double_as_longlong(rec.x) ^ flip));
                 }
                 A[w] = sacc;
             }
