@@ -159,17 +159,35 @@ def main():
         return
     n = args.n
     m = workloads.random_klocal(n=n)
+    log("initial state")
+    psi_host = workloads.random_state(n, m.init_seed)  # complex128, normalised in FP64
+    d128_0 = torch.from_numpy(psi_host).cuda()
+    dim = 1 << n
+    # tile sizes: the library's autotuner on this GPU (one timed step per
+    # candidate on a scratch copy of the state)
+    tune = {}
+    opts = sd.sd_plan_options_default()
+    h = sd.sd_hamiltonian_create(n, m.paulis, m.coeffs)
+    for name, dt_, tdt, cands in (("c64", sd.SD_C64, torch.complex64, [11, 12, 13]),
+                                  ("c128", sd.SD_C128, torch.complex128, [12, 13])):
+        log(f"autotune {name} tile size {cands}")
+        scratch = d128_0.to(tdt)
+        best, secs = sd.sd_autotune_tiles(h, dt_, scratch, m.dt, 1, 1, cands)
+        del scratch
+        size = best.tile_log2_c64 if dt_ == sd.SD_C64 else best.tile_log2_c128
+        if dt_ == sd.SD_C64:
+            opts.tile_log2_c64 = size
+        else:
+            opts.tile_log2_c128 = size
+        tune[name] = {"step_ms": {str(c): round(s * 1e3, 2) for c, s in zip(cands, secs)}, "chosen": size}
+    sd.sd_hamiltonian_destroy(h)
     t0 = time.time()
-    plan = sd.Plan(n, m.paulis, m.coeffs)
+    plan = sd.Plan(n, m.paulis, m.coeffs, opts)
     info = plan.info
     log(f"plan: {info.n_terms} terms, {info.n_groups} groups, passes/step c64 {info.passes_c64} "
         f"c128 {info.passes_c128}, paper-model passes {info.paper_model_passes}, "
         f"{time.time() - t0:.2f} s")
     plan.bind("cuda")
-    log("initial state")
-    psi_host = workloads.random_state(n, m.init_seed)  # complex128, normalised in FP64
-    d128_0 = torch.from_numpy(psi_host).cuda()
-    dim = 1 << n
     stream = torch.cuda.current_stream()
 
     def timed(state, steps, warmup):
@@ -245,7 +263,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "random_klocal_n28", "n_qubits": n, "terms": int(info.n_terms),
                    "groups": int(info.n_groups), "order": 1, "dt": m.dt,
-                   "storage": "complex64", "seed": 3, "init_seed": m.init_seed},
+                   "storage": "complex64", "seed": 3, "init_seed": m.init_seed,
+                   "tile_log2_c64": int(opts.tile_log2_c64), "tile_log2_c128": int(opts.tile_log2_c128)},
+        "autotune": tune,
         "c128_steps_per_s": round(sps128, 4),
         "c64_over_c128": round(sps64 / sps128, 3),
         "passes_per_step_c64": int(info.passes_c64),

@@ -102,7 +102,9 @@ typedef struct {
        Default 1. Affects the exported paper circuit only. */
     int32_t skip_rule;
     /* Largest tile (amplitudes staged on chip per work-group) as log2, per
-       dtype; 0 = built-in default (13 for both).  Range 6..13. */
+       dtype; 0 = built-in default (13 for both).  Range 6..13.  complex64
+       passes take the smallest tile of at least 2^10 that holds them, up to
+       this size; sd_autotune_tiles measures which maximum runs fastest. */
     int32_t tile_log2_c64;
     int32_t tile_log2_c128;
     /* Low qubits every tile must contain so that global accesses are whole
@@ -297,6 +299,22 @@ sd_status sd_expectation(const sd_plan_t *p, const void *state, sd_dtype dtype,
    SD_ERR_WORKSPACE (no workspace), SD_ERR_HIP. */
 sd_status sd_term_expectations(const sd_plan_t *p, const void *state, sd_dtype dtype,
                                double *out, void *stream);
+
+/* Autotuning of the tile size (the on-chip block of 2^D amplitudes a
+   work-group transforms) for one Hamiltonian on this GPU.  For each of the
+   n_candidates maximum tile sizes (log2, 6..13) a plan with the options
+   `base` (NULL: defaults) and that size for `dtype` is built and bound to a
+   workspace the call allocates and frees, one step is run as warm-up and
+   `steps` Trotter steps (dt, order) are timed with HIP events on `stream`.
+   state: device pointer to 2^n amplitudes of `dtype`, used as scratch (its
+   contents are evolved).  best: the options of the fastest candidate (base
+   with the winning size for `dtype`); seconds: host array of n_candidates
+   per-step times, or NULL.  Synchronises `stream`.  Errors: SD_ERR_ARG,
+   SD_ERR_RANGE (candidate out of range), SD_ERR_HIP, and those of sd_plan. */
+sd_status sd_autotune_tiles(const sd_hamiltonian *h, const sd_plan_options *base,
+                            sd_dtype dtype, void *state, double dt, int32_t order,
+                            int32_t steps, const int32_t *candidates, int32_t n_candidates,
+                            sd_plan_options *best, double *seconds, void *stream);
 
 /* FP64 reductions over 2^n amplitudes (device inputs, host outputs;
    synchronise `stream`).  sd_norm2: sum |a_x|^2.  sd_inner: sum conj(a_x) b_x

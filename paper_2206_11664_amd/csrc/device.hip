@@ -1473,6 +1473,66 @@ extern "C" sd_status sd_sync(void *stream) {
     return hip_check(hipGetLastError(), "sd_sync (async error)");
 }
 
+extern "C" sd_status sd_autotune_tiles(const sd_hamiltonian *h, const sd_plan_options *base,
+                                       sd_dtype dtype, void *state, double dt, int32_t order,
+                                       int32_t steps, const int32_t *candidates, int32_t n_candidates,
+                                       sd_plan_options *best, double *seconds, void *stream) {
+    if (!h || !state || !candidates || !best || n_candidates < 1 || steps < 1)
+        return fail(SD_ERR_ARG, "sd_autotune_tiles: bad argument");
+    if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_autotune_tiles: bad dtype");
+    for (int i = 0; i < n_candidates; ++i)
+        if (candidates[i] < kMinTileLog2 || candidates[i] > kMaxTileLog2)
+            return fail(SD_ERR_RANGE, "sd_autotune_tiles: candidate tile size out of range");
+    hipStream_t s = (hipStream_t)stream;
+    sd_plan_options opt;
+    sd_plan_options_default(&opt);
+    if (base) opt = *base;
+    double best_t = -1.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    sd_status r = hip_check(hipEventCreate(&e0), "event");
+    if (r == SD_OK) r = hip_check(hipEventCreate(&e1), "event");
+    for (int i = 0; i < n_candidates && r == SD_OK; ++i) {
+        sd_plan_options o = opt;
+        if (dtype == SD_C64) o.tile_log2_c64 = candidates[i];
+        else o.tile_log2_c128 = candidates[i];
+        if ((dtype == SD_C64 ? o.coalesce_log2_c64 : o.coalesce_log2_c128) >= candidates[i]) {
+            // (the coalescing default must stay below the tile)
+            if (dtype == SD_C64) o.coalesce_log2_c64 = std::min(4, candidates[i] - 1);
+            else o.coalesce_log2_c128 = std::min(3, candidates[i] - 1);
+        }
+        sd_plan_t *p = nullptr;
+        r = sd_plan(h, &o, &p);
+        if (r != SD_OK) break;
+        sd_plan_info info;
+        sd_plan_info_get(p, &info);
+        void *ws = nullptr;
+        r = hip_check(hipMalloc(&ws, (size_t)info.workspace_bytes), "autotune workspace");
+        if (r == SD_OK) r = sd_bind_workspace(p, ws, (size_t)info.workspace_bytes, stream);
+        if (r == SD_OK) r = sd_evolve(p, state, dtype, dt, 1, order, stream);
+        if (r == SD_OK) r = hip_check(hipEventRecord(e0, s), "event record");
+        if (r == SD_OK) r = sd_evolve(p, state, dtype, dt, steps, order, stream);
+        if (r == SD_OK) r = hip_check(hipEventRecord(e1, s), "event record");
+        if (r == SD_OK) r = hip_check(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        if (r == SD_OK) r = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+        if (ws) {
+            hipStreamSynchronize(s);
+            hipFree(ws);
+        }
+        sd_plan_destroy(p);
+        if (r != SD_OK) break;
+        const double t = (double)ms / 1e3 / steps;
+        if (seconds) seconds[i] = t;
+        if (best_t < 0 || t < best_t) {
+            best_t = t;
+            *best = o;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // ensemble
 // ---------------------------------------------------------------------------

@@ -31,7 +31,7 @@ EXPORTED = [
     "sd_plan_destroy",
     "sd_bind_workspace", "sd_evolve", "sd_expectation", "sd_term_expectations", "sd_norm2", "sd_inner",
     "sd_ensemble_create", "sd_ensemble_workspace_bytes", "sd_ensemble_bind_workspace",
-    "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_status_string",
+    "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_autotune_tiles", "sd_status_string",
     "sd_last_error", "sd_version",
 ]
 
@@ -132,6 +132,9 @@ def lib():
         "sd_ensemble_evolve": (st, [vp, ctypes.POINTER(vp), ctypes.c_double, i64, i32, vp]),
         "sd_ensemble_destroy": (None, [vp]),
         "sd_sync": (st, [vp]),
+        "sd_autotune_tiles": (st, [vp, ctypes.POINTER(sd_plan_options), ctypes.c_int, vp, ctypes.c_double,
+                                   i32, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(sd_plan_options),
+                                   dp, vp]),
         "sd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "sd_last_error": (ctypes.c_char_p, []),
         "sd_version": (ctypes.c_char_p, []),
@@ -386,6 +389,21 @@ def sd_ensemble_destroy(e: int):
 
 def sd_sync(stream=None):
     _check(lib().sd_sync(_stream(stream)))
+
+
+def sd_autotune_tiles(h: int, dtype: int, state, dt: float, order: int, steps: int,
+                      candidates: Sequence[int], base: Optional[sd_plan_options] = None,
+                      stream=None):
+    """Returns (options of the fastest candidate, per-step seconds of each)."""
+    cand = (ctypes.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    best = sd_plan_options()
+    secs = np.zeros(len(candidates))
+    _check(lib().sd_autotune_tiles(h, ctypes.byref(base) if base is not None else None, int(dtype),
+                                   _dev_ptr(state), float(dt), int(order), int(steps), cand,
+                                   len(candidates), ctypes.byref(best),
+                                   secs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   _stream(stream)))
+    return best, secs
 
 
 def sd_version() -> str:

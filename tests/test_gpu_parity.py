@@ -539,3 +539,38 @@ def test_shifted_round0_with_cz(n, seed, m, D, dtype):
     # slots (its outputs move by M d(t) as well as taking the sign)
     w = workloads.random_klocal(n=n, m=m, seed=seed, init_seed=2)
     check(w, dtype, 0.11, 3, 2, dict(tile_log2_c64=D, tile_log2_c128=D))
+
+
+def test_autotune_tiles():
+    # the tile-size autotuner returns one of its candidates with per-step
+    # times, and the plan it chooses evolves correctly; an ensemble built
+    # with the size tuned on its largest instance matches the oracle
+    m = workloads.random_klocal(n=16, m=200, seed=51, init_seed=52)
+    h = sd.sd_hamiltonian_create(m.n, m.paulis, m.coeffs)
+    scratch = torch.from_numpy(workloads.random_state(m.n, 53)).to(torch.complex64).cuda()
+    cands = [10, 11, 12, 13]
+    best, secs = sd.sd_autotune_tiles(h, sd.SD_C64, scratch, 0.05, 2, 1, cands)
+    print(f"[gpu] autotune n=16 c64: {dict(zip(cands, secs))} -> {best.tile_log2_c64}", flush=True)
+    assert best.tile_log2_c64 in cands and all(s > 0 for s in secs)
+    assert best.tile_log2_c64 == cands[int(np.argmin(secs))]
+    check(m, sd.SD_C64, 0.05, 2, 2, dict(tile_log2_c64=best.tile_log2_c64))
+    sd.sd_hamiltonian_destroy(h)
+    models = workloads.xxz_ensemble(count=6, seed=7, nmin=12, nmax=16, steps=10)
+    big = max(models, key=lambda w: w.n)
+    hb = sd.sd_hamiltonian_create(big.n, big.paulis, big.coeffs)
+    sb = torch.from_numpy(big.initial_state()).cuda()
+    bo, _ = sd.sd_autotune_tiles(hb, sd.SD_C128, sb, 0.05, 2, 1, [10, 11, 12])
+    sd.sd_hamiltonian_destroy(hb)
+    o = sd.sd_plan_options_default()
+    o.tile_log2_c128 = bo.tile_log2_c128
+    plans = [sd.Plan(w.n, w.paulis, w.coeffs, o).bind() for w in models]
+    ens = sd.sd_ensemble_create([p.p for p in plans], sd.SD_C128)
+    ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+    sd.sd_ensemble_bind_workspace(ens, ws)
+    states = [torch.from_numpy(w.initial_state()).cuda() for w in models]
+    sd.sd_ensemble_evolve(ens, states, 0.05, 10, 2)
+    torch.cuda.synchronize()
+    for w, s in zip(models, states):
+        want = oracle.evolve(w.n, w.paulis, w.coeffs, w.initial_state(), 0.05, 10, 2)
+        assert l2(s.cpu().numpy(), want) <= 1e-10, w.n
+    sd.sd_ensemble_destroy(ens)
