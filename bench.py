@@ -136,6 +136,9 @@ def main():
                     help="instead of the benchmark line: the paper's fully connected TFIM "
                          "or SYK Majorana sweep, grouped vs term by term (one JSON line per n)")
     ap.add_argument("--nstep", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="plan with the default tile sizes (2^13) instead of autotuning them; "
+                         "the profiled runs use this so that their traces hold the timed plan only")
     ap.add_argument("--nmin", type=int, default=12)
     ap.add_argument("--nmax", type=int, default=30)
     ap.add_argument("--calib-copy", action="store_true",
@@ -168,8 +171,9 @@ def main():
     tune = {}
     opts = sd.sd_plan_options_default()
     h = sd.sd_hamiltonian_create(n, m.paulis, m.coeffs)
-    for name, dt_, tdt, cands in (("c64", sd.SD_C64, torch.complex64, [11, 12, 13]),
-                                  ("c128", sd.SD_C128, torch.complex128, [12, 13])):
+    for name, dt_, tdt, cands in (() if args.no_autotune else
+                                  (("c64", sd.SD_C64, torch.complex64, [11, 12, 13]),
+                                   ("c128", sd.SD_C128, torch.complex128, [12, 13]))):
         log(f"autotune {name} tile size {cands}")
         scratch = d128_0.to(tdt)
         best, secs = sd.sd_autotune_tiles(h, dt_, scratch, m.dt, 1, 1, cands)
