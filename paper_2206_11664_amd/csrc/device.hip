@@ -1140,6 +1140,8 @@ static void init_device_props() {
     set_lds(k_pass<float2, 1>, lds_generic);
     set_lds(k_pass<double2, 0>, lds_generic);
     set_lds(k_pass<double2, 1>, lds_generic);
+    set_lds(k_pass<float2, 2>, lds_generic);
+    set_lds(k_pass<double2, 2>, lds_generic);
     const int lds = (int)kTileLdsMax;
     bool ok = true;
     auto prep = [&](auto kernel) {
