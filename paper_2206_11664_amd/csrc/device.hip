@@ -50,6 +50,17 @@ static void pack_program(const Program &P, int n, int64_t base_off, std::vector<
         d.n_tiles = (int64_t)1 << (n - p.D);
         d.term_off = base_off + toff;
         d.scale = std::ldexp(1.0, -p.rho);
+        {
+            // (exact: the scale is a power of two)
+            const double kc[7] = {1.0, -1.0 / 2.0, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0,
+                                  -1.0 / 3628800.0, 1.0 / 479001600.0};
+            const double ks[7] = {1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0,
+                                  -1.0 / 39916800.0, 1.0 / 6227020800.0};
+            for (int i = 0; i < 7; ++i) {
+                d.kcos[i] = d.scale * kc[i];
+                d.ksin[i] = d.scale * ks[i];
+            }
+        }
         for (int j = p.c; j < p.D; ++j) d.u_hi[j - p.c] = p.u[j];
         for (int j = 0; j < p.D; ++j) d.mr[j] = p.mr[j];
         for (int j = 0; j < p.rho; ++j) d.B[j] = p.B[j];
@@ -364,6 +375,25 @@ __device__ __forceinline__ void cis(double th, int halv, double &c, double &s) {
     }
 }
 
+// 2^-rho e^{i x} for |x| <= 1/4 and no double-angle steps: the polynomials
+// of cis with every coefficient multiplied by 2^-rho (kc, ks from the pass
+// record, constant term first; exact, the factor being a power of two), so
+// the result needs no separate scaling.  FULL: degrees 12/13, else 8/9.
+template <bool FULL>
+__device__ __forceinline__ void cis_scaled(double x, const double *kc, const double *ks, double &c,
+                                           double &s) {
+    constexpr int N = FULL ? 7 : 5;
+    const double x2 = x * x;
+    double pc = kc[N - 1], ps = ks[N - 1];
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) {
+        pc = fma(pc, x2, kc[i]);
+        ps = fma(ps, x2, ks[i]);
+    }
+    c = pc;
+    s = ps * x;
+}
+
 // butterflies on register bit L.  Forward: (a, c) -> (a + w c, a - w c) with
 // w = 1 or i (the S of that coordinate applied first).  Backward, the inverse
 // up to the factor 2: (A, C) -> (A + C, conj(w) (A - C)).
@@ -529,7 +559,9 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
             const uint64_t zt = ((const uint64_t *)(tb + o2))[k];
             const double cf = ((const double *)(tb + o2 + 8 * (int64_t)m))[k];
             trec[k] = make_double2(0.0, __longlong_as_double((long long)z));
-            tsrc[k] = make_double2(cf, __longlong_as_double((long long)zt));
+            // (evolution: the coefficient times -tau, so that the bucket
+            // sums are the phase angles themselves)
+            tsrc[k] = make_double2(MODE == 0 ? -tau * cf : cf, __longlong_as_double((long long)zt));
         }
     }
     const double scale = pd.scale;
@@ -896,9 +928,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
                     double cc, ss;
-                    cis<FULL>(-tau * A[j], 0, cc, ss);
-                    cc *= scale;
-                    ss *= scale;
+                    cis_scaled<FULL>(A[j], pd.kcos, pd.ksin, cc, ss);
                     const double ar = re[j], ai = im[j];
                     re[j] = fma(ar, cc, -ai * ss);
                     im[j] = fma(ar, ss, ai * cc);
@@ -907,7 +937,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
 #pragma unroll
                 for (int j = 0; j < kE; ++j) {
                     double cc, ss;
-                    cis<FULL>(-tau * A[j], halv, cc, ss);
+                    cis<FULL>(A[j], halv, cc, ss);
                     cc *= scale;
                     ss *= scale;
                     const double ar = re[j], ai = im[j];

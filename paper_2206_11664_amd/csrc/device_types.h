@@ -18,6 +18,8 @@ struct alignas(256) PassDev {
     int64_t n_tiles;    // 2^(n-D)
     int64_t term_off;   // byte offset of the term arrays from the workspace base
     double scale;       // 2^-rho
+    double kcos[7];     // 2^-rho times the Taylor coefficients of cos in x^2 (constant first)
+    double ksin[7];     // 2^-rho times those of sin(x)/x
     uint64_t u_hi[kMaxD];   // physical vectors of tile pivots c..D-1
     uint32_t mr[kMaxD];     // tile coordinates of each pivot vector
     uint32_t B[kMaxD];      // CZ/S quadratic form rows (rho used)
