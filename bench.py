@@ -11,6 +11,7 @@ the fidelity figure.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -123,6 +124,98 @@ def paper_sweep(args, torch, workloads, sd):
         del psi0, plans
 
 
+def ensemble_experiment(args, torch, workloads, sd):
+    """The ensemble workload on this GPU: 256 open XXZ chains, n_i ~ U{14..20}
+    (seed 4), Neel states, second order at dt = 0.05, evolved together by
+    sd_ensemble_evolve (one multi-instance tile launch per pass level, one
+    step replayed as a HIP graph).  Timed: --steps steps after --warmup, for
+    complex64 and complex128; beside it the same instances evolved one after
+    another with sd_evolve.  Algorithmic bytes: every pass of every instance
+    reads and writes its state once, 2 * 2^n_i * B bytes.  Accuracy: mean and
+    worst 1 - F between the complex64 and complex128 ensembles after the same
+    steps."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    models = workloads.xxz_ensemble()
+    dt, order = models[0].dt, models[0].order
+    log(f"ensemble: planning {len(models)} instances")
+    t0 = time.time()
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind("cuda") for m in models]
+    plan_s = time.time() - t0
+    amps = sum(1 << m.n for m in models)
+
+    def passes_per_step(plan, dtype):
+        # the order-2 schedule: groups 0..K-2 twice (half steps), K-1 once
+        per_group = collections.Counter(ps["group"] for ps in plan.passes(dtype))
+        K = int(plan.info.n_groups)
+        if K <= 1:
+            return sum(per_group.values())
+        return 2 * sum(per_group[g] for g in range(K - 1)) + per_group[K - 1]
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    res = {}
+    finals = {}
+    for name, dtype, tdt, B in (("c64", sd.SD_C64, torch.complex64, 8),
+                                ("c128", sd.SD_C128, torch.complex128, 16)):
+        log(f"ensemble {name}")
+        ens = sd.sd_ensemble_create([p.p for p in plans], dtype)
+        ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+        sd.sd_ensemble_bind_workspace(ens, ws)
+        states = [torch.from_numpy(m.initial_state()).to(tdt).cuda() for m in models]
+        run = lambda k: sd.sd_ensemble_evolve(ens, states, dt, k, order)
+        if args.warmup:
+            run(args.warmup)
+        sec = timed(run, args.steps)
+        launches = sum(passes_per_step(p, dtype) for p in plans)
+        step_bytes = sum(passes_per_step(p, dtype) * 2 * (1 << m.n) * B for p, m in zip(plans, models))
+        gbps = step_bytes * args.steps / sec / 1e9
+        # the same instances one after another (warm-up of the same length)
+        seq = [torch.from_numpy(m.initial_state()).to(tdt).cuda() for m in models]
+        ks = max(1, args.steps // 4)
+
+        def one_by_one(k):
+            for p, st in zip(plans, seq):
+                p.evolve(st, dt, k, order)
+        one_by_one(1)
+        sec_seq = timed(one_by_one, ks)
+        res[name] = {"steps_per_s": round(args.steps / sec, 3),
+                     "ms_per_step": round(1e3 * sec / args.steps, 4),
+                     "instance_passes_per_step": launches,
+                     "bytes_per_step": step_bytes,
+                     "hbm_gbps_algorithmic": round(gbps, 1),
+                     "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
+                     "one_by_one_steps_per_s": round(ks / sec_seq, 3),
+                     "ensemble_speedup_vs_one_by_one": round((args.steps / sec) / (ks / sec_seq), 2)}
+        finals[name] = states
+        log(f"ensemble {name}: {res[name]}")
+        sd.sd_ensemble_destroy(ens)
+        del ws, seq
+    fids = []
+    for m, a, b in zip(models, finals["c64"], finals["c128"]):
+        a2 = a.to(torch.complex128)
+        ov = sd.sd_inner(b, a2, m.n)
+        fids.append(abs(ov) ** 2 / (sd.sd_norm2(a2, m.n) * sd.sd_norm2(b, m.n)))
+    out = {"experiment": "ensemble", "metric": "ensemble Trotter steps/s (256 instances together)",
+           "unit": "steps/s", "steps": args.steps, "warmup": args.warmup,
+           "config": {"workload": "xxz_open_ensemble_256", "instances": len(models),
+                      "n_range": [min(m.n for m in models), max(m.n for m in models)],
+                      "amplitudes": amps, "order": order, "dt": dt, "seed": 4},
+           "plan_seconds": round(plan_s, 2), **res,
+           "accuracy_c64_vs_c128": {"steps": args.warmup + args.steps,
+                                    "mean_1_minus_F": float(1.0 - np.mean(fids)),
+                                    "max_1_minus_F": float(1.0 - np.min(fids))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,9 +225,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=320)
-    ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep"], default=None,
+    ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep", "ensemble"], default=None,
                     help="instead of the benchmark line: the paper's fully connected TFIM "
-                         "or SYK Majorana sweep, grouped vs term by term (one JSON line per n)")
+                         "or SYK Majorana sweep, grouped vs term by term (one JSON line per n), "
+                         "or the 256-instance XXZ ensemble (one JSON line)")
     ap.add_argument("--nstep", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true",
                     help="plan with the default tile sizes (2^13) instead of autotuning them; "
@@ -157,6 +251,9 @@ def main():
     from paper_2206_11664_amd import sd
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.experiment == "ensemble":
+        ensemble_experiment(args, torch, workloads, sd)
+        return
     if args.experiment:
         paper_sweep(args, torch, workloads, sd)
         return

@@ -379,9 +379,8 @@ __device__ __forceinline__ void cis(double th, int halv, double &c, double &s) {
 // of cis with every coefficient multiplied by 2^-rho (kc, ks from the pass
 // record, constant term first; exact, the factor being a power of two), so
 // the result needs no separate scaling.  FULL: degrees 12/13, else 8/9.
-template <bool FULL>
-__device__ __forceinline__ void cis_scaled(double x, const double *kc, const double *ks, double &c,
-                                           double &s) {
+template <bool FULL, typename CP>
+__device__ __forceinline__ void cis_scaled(double x, CP kc, CP ks, double &c, double &s) {
     constexpr int N = FULL ? 7 : 5;
     const double x2 = x * x;
     double pc = kc[N - 1], ps = ks[N - 1];
@@ -513,8 +512,8 @@ __device__ __forceinline__ void from_c128(double2 &o, double2 v) { o = v; }
 // run over the lowest address bits) and its mirrored inverse round writes
 // them straight back, so the tile crosses LDS only between rounds; a pass of
 // a single round never touches LDS for amplitudes.
-template <typename T, int MODE, typename OFF, bool GEN>
-__device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *__restrict__ pdp,
+template <typename T, int MODE, typename OFF, bool GEN, typename PDP = const PassDev *>
+__device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict__ pdp,
                                           const uint8_t *__restrict__ ws, double tau, int64_t t0,
                                           int64_t t1, int64_t stride, double &acc) {
     constexpr bool FULL = sizeof(T) == 16;
@@ -522,7 +521,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, const PassDev *
     // prefetch of the next tile: it would not fit two waves per SIMD
     constexpr bool PF = MODE == 0 && sizeof(T) == 8;
     extern __shared__ double2 lds_dyn[];
-    const PassDev &pd = *pdp;
+    const auto &pd = *pdp;
     const int D = pd.D, TL = D - kLE, m = pd.m, nr = pd.nr;
     const uint32_t T_ = blockDim.x;
     const uint32_t tid = threadIdx.x;
@@ -1045,6 +1044,14 @@ k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__
 // Ensemble level launch: segment i is one pass of one instance (its tiles are
 // items first_item .. first_item + n_tiles - 1 of a flat list); every block
 // takes a contiguous share of the items, so it changes instance rarely.
+template <typename P>
+__device__ __forceinline__ P *uniform_ptr(P *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
+}
+
 struct MultiSeg {
     void *state;
     const PassDev *pd;
@@ -1065,7 +1072,13 @@ k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
         const int64_t a = sg.first_item, b = sg.first_item + sg.n_tiles;
         const int64_t s0 = a > lo ? a : lo, s1 = b < hi ? b : hi;
         if (s0 >= s1) continue;
-        tile_pass<T, 0, uint32_t, GEN>((T *)sg.state, sg.pd, sg.ws, sg.tau, s0 - a, s1 - a, 1, acc);
+        // the record is read from a pointer held in memory; it is read-only
+        // while kernels run, so it is addressed as constant memory with a
+        // wave-uniform address: its fields then come in through scalar
+        // loads, as from k_tile's kernel argument
+        typedef const __attribute__((address_space(4))) PassDev *ConstRec;
+        tile_pass<T, 0, uint32_t, GEN, ConstRec>((T *)sg.state, (ConstRec)uniform_ptr(sg.pd), sg.ws,
+                                                 sg.tau, s0 - a, s1 - a, 1, acc);
     }
 }
 
@@ -1114,14 +1127,26 @@ __global__ void k_term_final(const double *__restrict__ partial, int count, int 
     out[k] = s;
 }
 
-// fixed-order final sum of `count` interleaved groups of `width` partials
-__global__ void k_final(const double *__restrict__ partial, int count, int width,
-                        double *__restrict__ out) {
-    if (threadIdx.x < width) {
+// final sum of `count` interleaved groups of `width` (1 or 2) partials in a
+// fixed order: thread t adds partials t, t + kFinalThreads, ... in turn, then
+// a binary tree of the same shape on every call combines the threads
+constexpr int kFinalThreads = 256;
+__global__ void __launch_bounds__(kFinalThreads)
+k_final(const double *__restrict__ partial, int count, int width, double *__restrict__ out) {
+    __shared__ double red[2][kFinalThreads];
+    const int t = threadIdx.x;
+    for (int w = 0; w < width; ++w) {
         double s = 0.0;
-        for (int i = 0; i < count; ++i) s += partial[i * width + threadIdx.x];
-        out[threadIdx.x] = s;
+        for (int i = t; i < count; i += kFinalThreads) s += partial[(int64_t)i * width + w];
+        red[w][t] = s;
     }
+    __syncthreads();
+    for (int h = kFinalThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int w = 0; w < width; ++w) red[w][t] += red[w][t + h];
+        __syncthreads();
+    }
+    if (t < width) out[t] = red[t][0];
 }
 
 __global__ void k_fill(double *__restrict__ p, int count, double v) {
@@ -1367,7 +1392,7 @@ extern "C" sd_status sd_expectation(const sd_plan_t *p, const void *state, sd_dt
         maxgrid = std::max<int>(maxgrid, (int)std::min<int64_t>((int64_t)1 << (p->n - P.passes[i].D),
                                                                  kPartialSlots / 2));
     }
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partial, maxgrid, 1, out);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kFinalThreads), 0, s, partial, maxgrid, 1, out);
     r = hip_check(hipGetLastError(), "final reduce");
     if (r != SD_OK) return r;
     r = hip_check(hipMemcpyAsync(energy, out, sizeof(double), hipMemcpyDeviceToHost, s), "copy energy");
@@ -1463,7 +1488,7 @@ extern "C" sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n, doub
         hipLaunchKernelGGL(k_norm2<float2>, dim3(grid), dim3(kBlock), 0, s, (const float2 *)state, dim, buf);
     else
         hipLaunchKernelGGL(k_norm2<double2>, dim3(grid), dim3(kBlock), 0, s, (const double2 *)state, dim, buf);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, buf, grid, 1, buf + 2 * kPartialSlots);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kFinalThreads), 0, s, buf, grid, 1, buf + 2 * kPartialSlots);
     r = hip_check(hipGetLastError(), "norm2 launch");
     if (r != SD_OK) return r;
     r = hip_check(hipMemcpyAsync(out, buf + 2 * kPartialSlots, sizeof(double), hipMemcpyDeviceToHost, s),
@@ -1489,7 +1514,7 @@ extern "C" sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int3
     else
         hipLaunchKernelGGL(k_inner<double2>, dim3(grid), dim3(kBlock), 0, s, (const double2 *)a,
                            (const double2 *)b, dim, buf);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, buf, grid, 2, buf + 2 * kPartialSlots);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kFinalThreads), 0, s, buf, grid, 2, buf + 2 * kPartialSlots);
     r = hip_check(hipGetLastError(), "inner launch");
     if (r != SD_OK) return r;
     r = hip_check(hipMemcpyAsync(out, buf + 2 * kPartialSlots, 2 * sizeof(double),
