@@ -26,6 +26,7 @@
 #include <unordered_map>
 #include <array>
 #include <cmath>
+#include <cstdint>
 
 #include "device_types.h"
 #include "sd_internal.h"
@@ -809,6 +810,14 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
 
 }  // namespace
 
+// Modelled time of one tile pass (about microseconds for a 2^28 state; a fit
+// over measured launches): a fixed part for the HBM round trip, one part per
+// register round (ceil(rho / kChunkBits) of them) and one per span coordinate.
+// Splits of a group into sub-groups are compared by the sum over their passes.
+static int64_t pass_cost(int rho) {
+    return 500 + 280 * ((std::max(rho, 1) + kChunkBits - 1) / kChunkBits) + 39 * (int64_t)rho;
+}
+
 sd_status compile_program(int n, const std::vector<Term> &T,
                           const std::vector<std::vector<int64_t>> &groups,
                           int D_max, int c, Program *out, bool shrink) {
@@ -825,9 +834,10 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         // X part already lies in the span joins (no growth), then the term
         // whose addition lets the most remaining terms in for free is added.
         // The growth is repeated with seeded random tie-breaks (and now and
-        // then the second-best term); the split with the fewest sub-groups,
-        // then the fewest register rounds (span dimensions / kChunkBits,
-        // rounded up), is kept.  Every split is exact: the terms commute.
+        // then the second-best term); the split of least modelled cost
+        // (pass_cost of each sub-group's X rank) is kept, and then sub-groups
+        // are dissolved into the others while that lowers the cost.  Every
+        // split is exact: the terms commute.
         auto grow = [&](uint64_t seed) {
             std::vector<std::vector<int64_t>> subs;
             std::vector<int64_t> rest(groups[g].begin(), groups[g].end());
@@ -838,7 +848,6 @@ sd_status compile_program(int n, const std::vector<Term> &T,
                 rng ^= rng << 17;
                 return rng;
             };
-            int rounds = 0;
             while (!rest.empty()) {
                 Echelon span;
                 for (int q = 0; q < cc; ++q) span.insert(1ull << q);
@@ -884,12 +893,37 @@ sd_status compile_program(int n, const std::vector<Term> &T,
                     cur.push_back(rest[best]);
                     rest.erase(rest.begin() + (long)best);
                 }
-                rounds += (std::max(1, span.dim() - cc) + kChunkBits - 1) / kChunkBits;
                 subs.push_back(std::move(cur));
             }
-            return std::make_pair(subs, rounds);
+            return subs;
         };
-        auto best_split = grow(0);
+        // a sub-group under construction: its tile space (low bits and X
+        // parts), the rank of its X parts alone, its terms
+        struct Sub {
+            Echelon tile, xs;
+            std::vector<int64_t> terms;
+        };
+        auto make_sub = [&](const std::vector<int64_t> &terms) {
+            Sub u;
+            for (int q = 0; q < cc; ++q) u.tile.insert(1ull << q);
+            for (int64_t k : terms) {
+                u.tile.insert(T[k].x);
+                u.xs.insert(T[k].x);
+            }
+            u.terms = terms;
+            return u;
+        };
+        auto split_cost = [&](const std::vector<std::vector<int64_t>> &subs) {
+            int64_t cost = 0;
+            for (auto &t : subs) {
+                Echelon xs;
+                for (int64_t k : t) xs.insert(T[k].x);
+                cost += pass_cost(xs.dim());
+            }
+            return cost;
+        };
+        std::vector<std::vector<int64_t>> best_split = grow(0);
+        int64_t best_cost = split_cost(best_split);
         // (no restarts when the plain greedy meets the bound set by the
         // dimension of the group's X span with the low bits)
         size_t lb = 1;
@@ -903,13 +937,114 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         // (each restart costs about size^2 reductions: fewer for big groups)
         const size_t gs = groups[g].size();
         const uint64_t restarts = std::max<uint64_t>(4, std::min<uint64_t>(48, 40000 / (gs * gs + 1)));
-        for (uint64_t r = 1; r <= restarts && gs > 1 && best_split.first.size() > lb; ++r) {
+        for (uint64_t r = 1; r <= restarts && gs > 1 && best_split.size() > lb; ++r) {
             auto cand = grow(0x9e3779b97f4a7c15ull * r + g * 0x632be59bd9b4e019ull + 1);
-            if (cand.first.size() < best_split.first.size() ||
-                (cand.first.size() == best_split.first.size() && cand.second < best_split.second))
+            const int64_t cost = split_cost(cand);
+            if (cost < best_cost) {
                 best_split = std::move(cand);
+                best_cost = cost;
+            }
         }
-        std::vector<std::vector<int64_t>> &subs = best_split.first;
+        // Dissolve sub-groups, smallest first: each of its terms goes to the
+        // other sub-group where it adds the least modelled cost (within the
+        // tile space and term limits); kept when every term finds a place and
+        // the total cost drops.
+        if (best_split.size() > 1) {
+            std::vector<Sub> cur;
+            for (auto &t : best_split) cur.push_back(make_sub(t));
+            auto total = [&](const std::vector<Sub> &v) {
+                int64_t cost = 0;
+                for (auto &u : v) cost += pass_cost(u.xs.dim());
+                return cost;
+            };
+            for (bool improved = true; improved && cur.size() > 1;) {
+                improved = false;
+                std::vector<size_t> order(cur.size());
+                for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+                std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+                    return cur[a].terms.size() < cur[b].terms.size();
+                });
+                const int64_t before = total(cur);
+                for (size_t sidx : order) {
+                    std::vector<Sub> trial = cur;
+                    bool placed = true;
+                    for (int64_t k : cur[sidx].terms) {
+                        const uint64_t x = T[k].x;
+                        size_t to = SIZE_MAX;
+                        int64_t delta_best = INT64_MAX;
+                        for (size_t j = 0; j < trial.size(); ++j) {
+                            if (j == sidx || (int)trial[j].terms.size() >= kMaxPassTerms) continue;
+                            if (!trial[j].tile.contains(x) && trial[j].tile.dim() >= Dcap) continue;
+                            const int rho = trial[j].xs.dim();
+                            const int rho_new = rho + (trial[j].xs.contains(x) ? 0 : 1);
+                            const int64_t delta = pass_cost(rho_new) - pass_cost(rho);
+                            if (delta < delta_best) {
+                                delta_best = delta;
+                                to = j;
+                            }
+                        }
+                        if (to == SIZE_MAX) {
+                            placed = false;
+                            break;
+                        }
+                        trial[to].tile.insert(x);
+                        trial[to].xs.insert(x);
+                        trial[to].terms.push_back(k);
+                    }
+                    if (!placed) continue;
+                    trial.erase(trial.begin() + (long)sidx);
+                    if (total(trial) < before) {
+                        cur = std::move(trial);
+                        improved = true;
+                        break;
+                    }
+                }
+            }
+            // Move single terms: a term whose X part lies outside the span of
+            // the rest of its sub-group moves to another sub-group when that
+            // lowers the cost (e.g. a span of 13 = 3 rounds drops to 12 = 2).
+            for (bool improved = true; improved && cur.size() > 1;) {
+                improved = false;
+                for (size_t sidx = 0; sidx < cur.size() && !improved; ++sidx) {
+                    const int rho_s = cur[sidx].xs.dim();
+                    const auto &ts = cur[sidx].terms;
+                    for (size_t ti = 0; ti < ts.size() && !improved; ++ti) {
+                        const uint64_t x = T[ts[ti]].x;
+                        Echelon wo;
+                        for (size_t u = 0; u < ts.size(); ++u)
+                            if (u != ti) wo.insert(T[ts[u]].x);
+                        if (wo.contains(x)) continue;  // its X part is spanned by the rest
+                        const int64_t gain_s = pass_cost(rho_s) - pass_cost(wo.dim());
+                        size_t to = SIZE_MAX;
+                        int64_t best_delta = 0;
+                        for (size_t j = 0; j < cur.size(); ++j) {
+                            if (j == sidx || (int)cur[j].terms.size() >= kMaxPassTerms) continue;
+                            if (!cur[j].tile.contains(x) && cur[j].tile.dim() >= Dcap) continue;
+                            const int rho = cur[j].xs.dim();
+                            const int rho_new = rho + (cur[j].xs.contains(x) ? 0 : 1);
+                            const int64_t delta = pass_cost(rho_new) - pass_cost(rho) - gain_s;
+                            if (delta < best_delta) {
+                                best_delta = delta;
+                                to = j;
+                            }
+                        }
+                        if (to == SIZE_MAX) continue;
+                        const int64_t k = ts[ti];
+                        std::vector<int64_t> rest_terms;
+                        for (size_t u = 0; u < ts.size(); ++u)
+                            if (u != ti) rest_terms.push_back(ts[u]);
+                        cur[to].tile.insert(x);
+                        cur[to].xs.insert(x);
+                        cur[to].terms.push_back(k);
+                        cur[sidx] = make_sub(rest_terms);
+                        improved = true;
+                    }
+                }
+            }
+            best_split.clear();
+            for (auto &u : cur) best_split.push_back(std::move(u.terms));
+        }
+        std::vector<std::vector<int64_t>> &subs = best_split;
         for (auto &s : subs) {
             PassHost ps;
             // shrink: the smallest tile (not below the register-round minimum)
