@@ -490,3 +490,69 @@ def test_register_rounds_shift_with_cz_matches_oracle(n, seed, m, D, dtype):
     got = round_emulator.evolve(psi0, w.n, passes, rounds, info.n_groups, 0.11, 1, 2)
     want = oracle.evolve(w.n, w.paulis, w.coeffs, psi0, 0.11, 1, 2)
     assert np.abs(got - want).max() < 1e-13
+
+
+# --- sub-group splits ---------------------------------------------------------------
+def _gf2_rank(vecs):
+    basis = []  # reduced rows, distinct leading bits
+    for v in vecs:
+        v = int(v)
+        for b in basis:
+            v = min(v, v ^ b)
+        if v:
+            basis.append(v)
+    return len(basis)
+
+
+@pytest.mark.parametrize("which", ["klocal28", "jw32", "syk12", "tfim20", "klocal_small_tiles"])
+def test_subgroup_splits_partition_groups(which):
+    # every group's passes (in plan order) hold each of the group's terms
+    # exactly once; each pass's span is the rank of its terms' X parts and its
+    # tile (those X parts and the low address bits) fits 2^tile_log2
+    opt = {}
+    if which == "klocal28":
+        m = workloads.random_klocal(n=28)
+    elif which == "jw32":
+        m = workloads.jw_fermionic(n=32)
+    elif which == "syk12":
+        m = workloads.syk_majorana(12)
+    elif which == "tfim20":
+        m = workloads.tfim_fully_connected(20)
+    else:
+        m = workloads.random_klocal(n=14, m=400, seed=11, init_seed=12)
+        opt = dict(tile_log2_c64=10, tile_log2_c128=10, coalesce_log2_c64=3, coalesce_log2_c128=2)
+    h, p = plan_for(m.n, m.paulis, m.coeffs, **opt)
+    _, xs, _, _, _ = sd.sd_hamiltonian_terms(h)
+    info = sd.sd_plan_info_get(p)
+    groups = groups_of(p)
+    for dtype in (sd.SD_C64, sd.SD_C128):
+        seen = [[] for _ in range(info.n_groups)]
+        for i in range(sd.sd_plan_pass_count(p, dtype)):
+            q = sd.sd_plan_export_pass(p, dtype, i)
+            ids = [int(t) for t in q["term_ids"]]
+            assert ids, "empty pass"
+            seen[q["group"]].append(ids)
+            x = [int(xs[t]) for t in ids]
+            assert q["rho"] == _gf2_rank(x)
+            low = [1 << b for b in range(q["coalesce_log2"])]
+            assert _gf2_rank(x + low) <= q["tile_log2"]
+        for g in range(info.n_groups):
+            got = [t for ids in seen[g] for t in ids]
+            assert sorted(got) == sorted(int(t) for t in groups[g]), f"group {g}"
+        # (passes of a group are consecutive: group ids never decrease)
+        order = [sd.sd_plan_export_pass(p, dtype, i)["group"] for i in range(sd.sd_plan_pass_count(p, dtype))]
+        assert order == sorted(order)
+    sd.sd_plan_destroy(p)
+    sd.sd_hamiltonian_destroy(h)
+
+
+def test_benchmark_split_cost_guard():
+    # the n = 28 benchmark's complex64 plan: pass and register-round counts
+    # (a regression guard on the sub-group split and the chunk packing)
+    m = workloads.random_klocal(n=28)
+    h, p = plan_for(m.n, m.paulis, m.coeffs)
+    npass = sd.sd_plan_pass_count(p, sd.SD_C64)
+    rounds = sum(sd.sd_plan_export_rounds(p, sd.SD_C64, i)["n_rounds"] for i in range(npass))
+    assert npass <= 158 and rounds <= 277, (npass, rounds)
+    sd.sd_plan_destroy(p)
+    sd.sd_hamiltonian_destroy(h)
