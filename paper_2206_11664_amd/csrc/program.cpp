@@ -814,6 +814,8 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
 // over measured launches): a fixed part for the HBM round trip, one part per
 // register round (ceil(rho / kChunkBits) of them) and one per span coordinate.
 // Splits of a group into sub-groups are compared by the sum over their passes.
+constexpr int kShrinkMaxTerms = 32;  // passes with more Lambda terms keep the full tile
+
 static int64_t pass_cost(int rho) {
     return 500 + 280 * ((std::max(rho, 1) + kChunkBits - 1) / kChunkBits) + 39 * (int64_t)rho;
 }
@@ -1048,9 +1050,12 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         for (auto &s : subs) {
             PassHost ps;
             // shrink: the smallest tile (not below the register-round minimum)
-            // that holds the sub-group's span and low bits
+            // that holds the sub-group's span and low bits.  A pass with many
+            // Lambda terms keeps the full tile: every thread runs the whole
+            // term loop, and the small blocks of a shrunk tile (each with its
+            // own term tables in LDS, so fewer waves per CU) run it slower.
             int Dt = Dcap;
-            if (shrink) {
+            if (shrink && (int)s.size() <= kShrinkMaxTerms) {
                 Echelon sp;
                 for (int q = 0; q < cc; ++q) sp.insert(1ull << q);
                 for (int64_t k : s) sp.insert(T[k].x);
