@@ -959,87 +959,95 @@ sd_status compile_program(int n, const std::vector<Term> &T,
                 for (auto &u : v) cost += pass_cost(u.xs.dim());
                 return cost;
             };
-            for (bool improved = true; improved && cur.size() > 1;) {
-                improved = false;
-                std::vector<size_t> order(cur.size());
-                for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-                std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-                    return cur[a].terms.size() < cur[b].terms.size();
-                });
-                const int64_t before = total(cur);
-                for (size_t sidx : order) {
-                    std::vector<Sub> trial = cur;
-                    bool placed = true;
-                    for (int64_t k : cur[sidx].terms) {
-                        const uint64_t x = T[k].x;
-                        size_t to = SIZE_MAX;
-                        int64_t delta_best = INT64_MAX;
-                        for (size_t j = 0; j < trial.size(); ++j) {
-                            if (j == sidx || (int)trial[j].terms.size() >= kMaxPassTerms) continue;
-                            if (!trial[j].tile.contains(x) && trial[j].tile.dim() >= Dcap) continue;
-                            const int rho = trial[j].xs.dim();
-                            const int rho_new = rho + (trial[j].xs.contains(x) ? 0 : 1);
-                            const int64_t delta = pass_cost(rho_new) - pass_cost(rho);
-                            if (delta < delta_best) {
-                                delta_best = delta;
-                                to = j;
+            // (the two moves alternate until neither lowers the cost: each
+            // accepted move lowers it, so this ends)
+            for (bool again = true; again;) {
+                again = false;
+                for (bool improved = true; improved && cur.size() > 1;) {
+                    improved = false;
+                    std::vector<size_t> order(cur.size());
+                    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+                    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+                        return cur[a].terms.size() < cur[b].terms.size();
+                    });
+                    const int64_t before = total(cur);
+                    for (size_t sidx : order) {
+                        std::vector<Sub> trial = cur;
+                        bool placed = true;
+                        for (int64_t k : cur[sidx].terms) {
+                            const uint64_t x = T[k].x;
+                            size_t to = SIZE_MAX;
+                            int64_t delta_best = INT64_MAX;
+                            for (size_t j = 0; j < trial.size(); ++j) {
+                                if (j == sidx || (int)trial[j].terms.size() >= kMaxPassTerms) continue;
+                                if (!trial[j].tile.contains(x) && trial[j].tile.dim() >= Dcap) continue;
+                                const int rho = trial[j].xs.dim();
+                                const int rho_new = rho + (trial[j].xs.contains(x) ? 0 : 1);
+                                const int64_t delta = pass_cost(rho_new) - pass_cost(rho);
+                                if (delta < delta_best) {
+                                    delta_best = delta;
+                                    to = j;
+                                }
                             }
+                            if (to == SIZE_MAX) {
+                                placed = false;
+                                break;
+                            }
+                            trial[to].tile.insert(x);
+                            trial[to].xs.insert(x);
+                            trial[to].terms.push_back(k);
                         }
-                        if (to == SIZE_MAX) {
-                            placed = false;
+                        if (!placed) continue;
+                        trial.erase(trial.begin() + (long)sidx);
+                        if (total(trial) < before) {
+                            cur = std::move(trial);
+                            improved = true;
                             break;
                         }
-                        trial[to].tile.insert(x);
-                        trial[to].xs.insert(x);
-                        trial[to].terms.push_back(k);
-                    }
-                    if (!placed) continue;
-                    trial.erase(trial.begin() + (long)sidx);
-                    if (total(trial) < before) {
-                        cur = std::move(trial);
-                        improved = true;
-                        break;
                     }
                 }
-            }
-            // Move single terms: a term whose X part lies outside the span of
-            // the rest of its sub-group moves to another sub-group when that
-            // lowers the cost (e.g. a span of 13 = 3 rounds drops to 12 = 2).
-            for (bool improved = true; improved && cur.size() > 1;) {
-                improved = false;
-                for (size_t sidx = 0; sidx < cur.size() && !improved; ++sidx) {
-                    const int rho_s = cur[sidx].xs.dim();
-                    const auto &ts = cur[sidx].terms;
-                    for (size_t ti = 0; ti < ts.size() && !improved; ++ti) {
-                        const uint64_t x = T[ts[ti]].x;
-                        Echelon wo;
-                        for (size_t u = 0; u < ts.size(); ++u)
-                            if (u != ti) wo.insert(T[ts[u]].x);
-                        if (wo.contains(x)) continue;  // its X part is spanned by the rest
-                        const int64_t gain_s = pass_cost(rho_s) - pass_cost(wo.dim());
-                        size_t to = SIZE_MAX;
-                        int64_t best_delta = 0;
-                        for (size_t j = 0; j < cur.size(); ++j) {
-                            if (j == sidx || (int)cur[j].terms.size() >= kMaxPassTerms) continue;
-                            if (!cur[j].tile.contains(x) && cur[j].tile.dim() >= Dcap) continue;
-                            const int rho = cur[j].xs.dim();
-                            const int rho_new = rho + (cur[j].xs.contains(x) ? 0 : 1);
-                            const int64_t delta = pass_cost(rho_new) - pass_cost(rho) - gain_s;
-                            if (delta < best_delta) {
-                                best_delta = delta;
-                                to = j;
+                // Move single terms: a term whose X part lies outside the span of
+                // the rest of its sub-group moves to another sub-group when that
+                // lowers the cost (e.g. a span of 13 = 3 rounds drops to 12 = 2).
+                for (bool improved = true; improved && cur.size() > 1;) {
+                    improved = false;
+                    for (size_t sidx = 0; sidx < cur.size() && !improved; ++sidx) {
+                        const int rho_s = cur[sidx].xs.dim();
+                        const auto &ts = cur[sidx].terms;
+                        // (a lone term is never moved: that would leave an empty
+                        // sub-group; dissolving above covers that case)
+                        if (ts.size() < 2) continue;
+                        for (size_t ti = 0; ti < ts.size() && !improved; ++ti) {
+                            const uint64_t x = T[ts[ti]].x;
+                            Echelon wo;
+                            for (size_t u = 0; u < ts.size(); ++u)
+                                if (u != ti) wo.insert(T[ts[u]].x);
+                            if (wo.contains(x)) continue;  // its X part is spanned by the rest
+                            const int64_t gain_s = pass_cost(rho_s) - pass_cost(wo.dim());
+                            size_t to = SIZE_MAX;
+                            int64_t best_delta = 0;
+                            for (size_t j = 0; j < cur.size(); ++j) {
+                                if (j == sidx || (int)cur[j].terms.size() >= kMaxPassTerms) continue;
+                                if (!cur[j].tile.contains(x) && cur[j].tile.dim() >= Dcap) continue;
+                                const int rho = cur[j].xs.dim();
+                                const int rho_new = rho + (cur[j].xs.contains(x) ? 0 : 1);
+                                const int64_t delta = pass_cost(rho_new) - pass_cost(rho) - gain_s;
+                                if (delta < best_delta) {
+                                    best_delta = delta;
+                                    to = j;
+                                }
                             }
+                            if (to == SIZE_MAX) continue;
+                            const int64_t k = ts[ti];
+                            std::vector<int64_t> rest_terms;
+                            for (size_t u = 0; u < ts.size(); ++u)
+                                if (u != ti) rest_terms.push_back(ts[u]);
+                            cur[to].tile.insert(x);
+                            cur[to].xs.insert(x);
+                            cur[to].terms.push_back(k);
+                            cur[sidx] = make_sub(rest_terms);
+                            improved = again = true;
                         }
-                        if (to == SIZE_MAX) continue;
-                        const int64_t k = ts[ti];
-                        std::vector<int64_t> rest_terms;
-                        for (size_t u = 0; u < ts.size(); ++u)
-                            if (u != ti) rest_terms.push_back(ts[u]);
-                        cur[to].tile.insert(x);
-                        cur[to].xs.insert(x);
-                        cur[to].terms.push_back(k);
-                        cur[sidx] = make_sub(rest_terms);
-                        improved = true;
                     }
                 }
             }

@@ -504,7 +504,8 @@ def _gf2_rank(vecs):
     return len(basis)
 
 
-@pytest.mark.parametrize("which", ["klocal28", "jw32", "syk12", "tfim20", "klocal_small_tiles"])
+@pytest.mark.parametrize("which", ["klocal28", "jw32", "syk12", "tfim20", "klocal_small_tiles"]
+                         + [f"fuzz{i}" for i in range(6)])
 def test_subgroup_splits_partition_groups(which):
     # every group's passes (in plan order) hold each of the group's terms
     # exactly once; each pass's span is the rank of its terms' X parts and its
@@ -518,9 +519,16 @@ def test_subgroup_splits_partition_groups(which):
         m = workloads.syk_majorana(12)
     elif which == "tfim20":
         m = workloads.tfim_fully_connected(20)
-    else:
+    elif which == "klocal_small_tiles":
         m = workloads.random_klocal(n=14, m=400, seed=11, init_seed=12)
         opt = dict(tile_log2_c64=10, tile_log2_c128=10, coalesce_log2_c64=3, coalesce_log2_c128=2)
+    else:
+        # tiny tiles: groups split into many sub-groups, so the split's local
+        # moves (dissolving sub-groups, moving single terms) run often
+        i = int(which[4:])
+        m = workloads.random_klocal(n=10 + i, m=150 + 40 * i, seed=100 + i, init_seed=1)
+        opt = dict(tile_log2_c64=6 + i % 3, tile_log2_c128=6 + i % 3,
+                   coalesce_log2_c64=i % 3, coalesce_log2_c128=i % 2)
     h, p = plan_for(m.n, m.paulis, m.coeffs, **opt)
     _, xs, _, _, _ = sd.sd_hamiltonian_terms(h)
     info = sd.sd_plan_info_get(p)
