@@ -326,7 +326,11 @@ sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int32_t n_qubit
 
 /* Ensemble of independent instances (uneven sizes allowed), evolved together.
    plans: `count` plans, each with a bound workspace; states: host array of
-   `count` device pointers.  One launch per pass level per step. */
+   `count` device pointers.  One launch per pass level per step.
+   sd_ensemble_workspace_bytes: the device bytes for the per-level segment
+   tables, enough for every order (1, 2, 4); the caller allocates them
+   (256-byte aligned) and binds them with sd_ensemble_bind_workspace before
+   sd_ensemble_evolve (SD_ERR_WORKSPACE otherwise). */
 sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t count,
                              sd_dtype dtype, sd_ensemble **out);
 sd_status sd_ensemble_workspace_bytes(const sd_ensemble *e, int64_t *bytes);

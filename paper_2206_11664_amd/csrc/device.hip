@@ -1650,7 +1650,9 @@ extern "C" sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t c
             return fail(SD_ERR_ARG, "sd_ensemble_create: null plan");
         }
         e->plans.push_back(plans[i]);
-        e->max_levels = std::max<int>(e->max_levels, (int)step_passes(plans[i], dtype, 2).size());
+        // (segment tables for the longest step schedule, order 4's, so that
+        // one workspace serves every order)
+        e->max_levels = std::max<int>(e->max_levels, (int)step_passes(plans[i], dtype, 4).size());
     }
     e->dtype = dtype;
     e->ws_needed = ((int64_t)e->max_levels * count * (int64_t)sizeof(MultiSeg) + 255) / 256 * 256;

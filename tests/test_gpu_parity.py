@@ -389,6 +389,53 @@ def test_config4_full_ensemble():
         assert e128 <= 1e-10 and e64 <= 1e-5
 
 
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+@pytest.mark.parametrize("order", [1, 4])
+def test_ensemble_of_mixed_workloads(order, dtype):
+    # instances of different kinds in one ensemble (passes with a shifted
+    # round 0, CZ inside a chunk, staged I/O, split groups, 2^10 tiles), a
+    # change of dt between calls (the step graph is captured again): every
+    # instance matches the oracle and its own sd_evolve
+    specs = [(workloads.random_klocal(n=12, m=300, seed=3, init_seed=2),
+              dict(tile_log2_c64=10, tile_log2_c128=10)),
+             (workloads.random_klocal(n=14, m=300, seed=14, init_seed=2), {}),
+             (workloads.random_klocal(n=13, m=120, seed=21, init_seed=4), {}),
+             (workloads.jw_fermionic(n=12, total=700), {}),
+             (workloads.tfim_chain(12), {})]
+    plans = []
+    for m, o in specs:
+        opts = sd.sd_plan_options_default()
+        for k, v in o.items():
+            setattr(opts, k, v)
+        plans.append(sd.Plan(m.n, m.paulis, m.coeffs, opts).bind())
+    models = [m for m, _ in specs]
+    print(f"[gpu] mixed ensemble order {order} dtype {dtype}: sizes {[m.n for m in models]}", flush=True)
+    ens = sd.sd_ensemble_create([p.p for p in plans], dtype)
+    ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+    sd.sd_ensemble_bind_workspace(ens, ws)
+    psi0 = [workloads.random_state(m.n, 60 + i) for i, m in enumerate(models)]
+    states = [torch.from_numpy(a).to(TDT[dtype]).cuda() for a in psi0]
+    singles = [s.clone() for s in states]
+    sd.sd_ensemble_evolve(ens, states, 0.03, 3, order)
+    sd.sd_ensemble_evolve(ens, states, 0.02, 2, order)
+    for p, s in zip(plans, singles):
+        p.evolve(s, 0.03, 3, order)
+        p.evolve(s, 0.02, 2, order)
+    torch.cuda.synchronize()
+    for i, (m, s, s1) in enumerate(zip(models, states, singles)):
+        want = oracle.evolve(m.n, m.paulis, m.coeffs, psi0[i], 0.03, 3, order)
+        want = oracle.evolve(m.n, m.paulis, m.coeffs, want, 0.02, 2, order)
+        err = l2(s.cpu().numpy().astype(np.complex128), want)
+        err1 = l2(s1.cpu().numpy().astype(np.complex128), want)
+        diff = float((s - s1).abs().max())
+        print(f"[gpu]   instance {i} n={m.n}: L2 ensemble {err:.3e} single {err1:.3e} "
+              f"max|ensemble - single| {diff:.3e}", flush=True)
+        assert err <= TOL[dtype] and err1 <= TOL[dtype], (i, m.n, err, err1)
+        assert diff <= (1e-12 if dtype == sd.SD_C128 else 1e-6), (i, m.n, diff)
+    sd.sd_ensemble_destroy(ens)
+
+
 def _xspan_basis(xs):
     rows, basis = [], []
     for v in xs:

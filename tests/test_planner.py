@@ -564,3 +564,10 @@ def test_benchmark_split_cost_guard():
     assert npass <= 158 and rounds <= 277, (npass, rounds)
     sd.sd_plan_destroy(p)
     sd.sd_hamiltonian_destroy(h)
+
+
+def test_jw_generator_rejects_impossible_totals():
+    # asking for more distinct strings than exist raises instead of drawing forever
+    with pytest.raises(ValueError):
+        workloads.jw_fermionic(n=12)
+    assert len(workloads.jw_fermionic(n=12, total=2000).paulis) == 2000

@@ -198,6 +198,12 @@ def jw_fermionic(n: int = 32, total: int = 10000, seed: int = 5,
             add(_dense(n, {i: "Z", j: "Z"}))
     for i in range(n):
         add(_dense(n, {i: "Z"}))
+    # (at most 16 C(n, 4) distinct double-excitation strings exist: ask for
+    # no more than there are, or the draw below would never end)
+    n_dbl = 16 * (n * (n - 1) * (n - 2) * (n - 3) // 24)
+    if total > len(paulis) + n_dbl:
+        raise ValueError(f"jw_fermionic: total={total} exceeds the {len(paulis) + n_dbl} "
+                         f"distinct strings available at n={n}")
     while len(paulis) < total:
         q = sorted(int(v) for v in rng.choice(n, size=4, replace=False))
         ops = {}
