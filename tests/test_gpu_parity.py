@@ -263,11 +263,12 @@ def test_ensemble_of_uneven_instances(dtype):
 
 @pytest.mark.parametrize("mode", [sd.SD_MODE_PAPER_LAYERS, sd.SD_MODE_TERMWISE])
 @pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
-def test_reference_modes(mode, dtype):
+@pytest.mark.parametrize("order", [2, 4])
+def test_reference_modes(mode, dtype, order):
     # the paper's layer-by-layer circuit execution and the term-by-term
     # baseline give the same state as the oracle (and as the tiles)
     m = workloads.random_klocal(n=12, m=120, seed=21, init_seed=22)
-    check(m, dtype, 0.05, 3, 2, dict(mode=mode))
+    check(m, dtype, 0.05, 3, order, dict(mode=mode))
 
 
 # one large commuting group per case: X-span rank rho up to 13 (four register
