@@ -8,7 +8,9 @@ complex64 path (FP32 amplitudes, FP64 phase and butterflies) gives `value`;
 the complex128 path is timed beside it and serves as the FP64 reference for
 the fidelity figure.
 
-Prints one JSON line on stdout; progress goes to stderr.
+Prints one JSON line on stdout; progress goes to stderr.  --experiment
+tfim_sweep | syk_sweep runs the paper's two experiments instead (one line per
+n); --experiment ensemble the 256-instance XXZ ensemble (one line).
 """
 import argparse
 import collections
