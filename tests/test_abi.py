@@ -52,3 +52,12 @@ def test_evolve_rejects_bad_arguments_without_device():
     assert L.sd_bind_workspace(p, 8, 16, None) == sd.SD_ERR_WORKSPACE      # too small
     sd.sd_plan_destroy(p)
     sd.sd_hamiltonian_destroy(h)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark runs on one GPU; asking for more exits at once with a message
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
