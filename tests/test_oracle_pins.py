@@ -330,3 +330,27 @@ def test_fourth_order_schedule_is_symmetric_and_sums_to_dt():
             assert abs(sum(f for h, f in seq if h == g) - 1.0) < 1e-14
         assert [h for h, _ in seq] == [h for h, _ in reversed(seq)]
         assert all(abs(a[1] - b[1]) < 1e-15 for a, b in zip(seq, reversed(seq)))
+
+
+def test_trotter_energy_error_is_bounded_and_of_the_right_order():
+    # a product formula of order p conserves a Hamiltonian within O(dt^p) of
+    # H, so <H> oscillates within O(dt^p) of its start instead of drifting:
+    # halving dt shrinks the largest deviation ~2x (order 1) and ~4x
+    # (order 2), and the second half of a long run stays near the first
+    # (open XXZ chain, three groups, T = 20)
+    m = workloads.xxz_chain(n=8)
+    psi0 = workloads.random_state(8, 3)
+    e0 = oracle.energy(8, m.paulis, m.coeffs, psi0)
+    for order, lo, hi in ((1, 1.6, 2.5), (2, 3.2, 5.0)):
+        dev = {}
+        for dt in (0.1, 0.05):
+            k = int(round(0.5 / dt))
+            psi = psi0.copy()
+            d = []
+            for _ in range(40):
+                psi = oracle.evolve(8, m.paulis, m.coeffs, psi, dt, k, order)
+                d.append(abs(oracle.energy(8, m.paulis, m.coeffs, psi) - e0))
+            dev[dt] = np.array(d)
+            assert dev[dt][20:].max() <= 1.8 * dev[dt][:20].max(), (order, dt)
+        ratio = dev[0.1].max() / dev[0.05].max()
+        assert lo < ratio < hi, (order, ratio)
