@@ -102,13 +102,18 @@ typedef struct {
        Default 1. Affects the exported paper circuit only. */
     int32_t skip_rule;
     /* Largest tile (amplitudes staged on chip per work-group) as log2, per
-       dtype; 0 = built-in default (13 for both).  Range 6..13.  complex64
+       dtype.  Range 6..13; the default (sd_plan_options_default) is 13 for
+       both, and values outside the range are SD_ERR_RANGE.  complex64
        passes take the smallest tile of at least 2^10 that holds them, up to
-       this size; sd_autotune_tiles measures which maximum runs fastest. */
+       this size; sd_autotune_tiles measures which maximum runs fastest.
+       Callers start from sd_plan_options_default and change fields: a
+       zero-filled struct is not the default. */
     int32_t tile_log2_c64;
     int32_t tile_log2_c128;
     /* Low qubits every tile must contain so that global accesses are whole
-       cache lines; 0 = default (4 for c64 = 128 B, 3 for c128 = 128 B). */
+       runs of 2^c amplitudes.  Range 0..6 and below the tile size; 0 means
+       no such qubits (not the default).  Default 4 for c64 (128 B runs) and
+       3 for c128 (128 B). */
     int32_t coalesce_log2_c64;
     int32_t coalesce_log2_c128;
     /* Execution mode of sd_evolve (sd_expectation always uses the tiles):
@@ -303,26 +308,43 @@ sd_status sd_term_expectations(const sd_plan_t *p, const void *state, sd_dtype d
 /* Autotuning of the tile size (the on-chip block of 2^D amplitudes a
    work-group transforms) for one Hamiltonian on this GPU.  For each of the
    n_candidates maximum tile sizes (log2, 6..13) a plan with the options
-   `base` (NULL: defaults) and that size for `dtype` is built and bound to a
-   workspace the call allocates and frees, one step is run as warm-up and
-   `steps` Trotter steps (dt, order) are timed with HIP events on `stream`.
-   state: device pointer to 2^n amplitudes of `dtype`, used as scratch (its
-   contents are evolved).  best: the options of the fastest candidate (base
-   with the winning size for `dtype`); seconds: host array of n_candidates
-   per-step times, or NULL.  Synchronises `stream`.  Errors: SD_ERR_ARG,
-   SD_ERR_RANGE (candidate out of range), SD_ERR_HIP, and those of sd_plan. */
+   `base` (NULL: defaults) and that size for `dtype` is built and bound to the
+   caller's `workspace`, one step is run as warm-up and `steps` Trotter steps
+   (dt, order) are timed with HIP events on `stream`.  workspace: caller-owned
+   device memory, 256-byte aligned, of at least the bytes that
+   sd_autotune_workspace_bytes reports for the same h, base, dtype and
+   candidates (the largest plan workspace among the candidates); the library
+   allocates no device memory.  state: device pointer to 2^n amplitudes of
+   `dtype`, used as scratch (its contents are evolved).  best: the options of
+   the fastest candidate (base with the winning size for `dtype`); seconds:
+   host array of n_candidates per-step times, or NULL.  Synchronises
+   `stream`.  Errors: SD_ERR_ARG, SD_ERR_RANGE (candidate out of range),
+   SD_ERR_WORKSPACE (workspace too small or misaligned), SD_ERR_HIP, and
+   those of sd_plan. */
+sd_status sd_autotune_workspace_bytes(const sd_hamiltonian *h, const sd_plan_options *base,
+                                      sd_dtype dtype, const int32_t *candidates,
+                                      int32_t n_candidates, int64_t *bytes);
 sd_status sd_autotune_tiles(const sd_hamiltonian *h, const sd_plan_options *base,
                             sd_dtype dtype, void *state, double dt, int32_t order,
                             int32_t steps, const int32_t *candidates, int32_t n_candidates,
+                            void *workspace, size_t workspace_bytes,
                             sd_plan_options *best, double *seconds, void *stream);
 
 /* FP64 reductions over 2^n amplitudes (device inputs, host outputs;
    synchronise `stream`).  sd_norm2: sum |a_x|^2.  sd_inner: sum conj(a_x) b_x
-   written to out[0] (re), out[1] (im). */
+   written to out[0] (re), out[1] (im).  Per-block partial sums go to the
+   caller's `scratch`: device memory of at least
+   sd_reduction_scratch_bytes() bytes, 8-byte aligned, not used by other
+   work while the call runs; its contents are overwritten.  The partial sums
+   are combined in a fixed order, so equal inputs give bit-identical results.
+   Errors: SD_ERR_ARG (null pointers, bad dtype), SD_ERR_RANGE (n_qubits
+   outside 0..40), SD_ERR_WORKSPACE (scratch too small or misaligned),
+   SD_ERR_HIP. */
+int64_t sd_reduction_scratch_bytes(void);
 sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n_qubits,
-                   double *out, void *stream);
+                   double *out, void *scratch, size_t scratch_bytes, void *stream);
 sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int32_t n_qubits,
-                   double *out, void *stream);
+                   double *out, void *scratch, size_t scratch_bytes, void *stream);
 
 /* Ensemble of independent instances (uneven sizes allowed), evolved together.
    plans: `count` plans, each with a bound workspace; states: host array of

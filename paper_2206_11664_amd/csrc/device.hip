@@ -1327,14 +1327,17 @@ extern "C" sd_status sd_bind_workspace(sd_plan_t *p, void *dev_ptr, size_t bytes
         }
     }
     if (!p->layer_data.empty()) {
-        sd_status st = hip_check(hipMemcpy((uint8_t *)dev_ptr + p->ws_off_layers, p->layer_data.data(),
-                                           p->layer_data.size() * sizeof(uint64_t), hipMemcpyHostToDevice),
+        sd_status st = hip_check(hipMemcpyAsync((uint8_t *)dev_ptr + p->ws_off_layers, p->layer_data.data(),
+                                                p->layer_data.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                                s),
                                  "layer table upload");
+        if (st == SD_OK) st = hip_check(hipStreamSynchronize(s), "layer table upload sync");
         if (st != SD_OK) return st;
     }
     p->ws = dev_ptr;
     p->ws_bytes = bytes;
     p->bound = true;
+    ++p->bind_epoch;
     return SD_OK;
 }
 
@@ -1450,46 +1453,56 @@ extern "C" sd_status sd_term_expectations(const sd_plan_t *p, const void *state,
     return SD_OK;
 }
 
-namespace {
-// small per-thread scratch for the stand-alone reductions
-struct RedScratch {
-    double *buf = nullptr;
-    int dev = -1;
-};
-thread_local RedScratch g_red;
+// Per-block partial sums of the stand-alone reductions: up to kPartialSlots
+// blocks, two values each (sd_inner), then the two final values.
+constexpr int64_t kReductionScratchBytes = (int64_t)(2 * kPartialSlots + 64) * (int64_t)sizeof(double);
 
-sd_status red_scratch(double **out) {
-    int dev = 0;
-    sd_status r = hip_check(hipGetDevice(&dev), "hipGetDevice");
-    if (r != SD_OK) return r;
-    if (!g_red.buf || g_red.dev != dev) {
-        r = hip_check(hipMalloc((void **)&g_red.buf, (kPartialSlots * 2 + 64) * sizeof(double)),
-                      "reduction scratch");
-        if (r != SD_OK) return r;
-        g_red.dev = dev;
-    }
-    *out = g_red.buf;
+static sd_status check_scratch(void *scratch, size_t bytes, const char *who) {
+    if (!scratch) return fail(SD_ERR_ARG, std::string(who) + ": null scratch");
+    if ((int64_t)bytes < kReductionScratchBytes)
+        return fail(SD_ERR_WORKSPACE, std::string(who) + ": scratch of " + std::to_string(bytes) +
+                                          " bytes < required " + std::to_string(kReductionScratchBytes));
+    if (((uintptr_t)scratch) & 7) return fail(SD_ERR_WORKSPACE, std::string(who) + ": scratch not 8-byte aligned");
     return SD_OK;
 }
-}  // namespace
 
-extern "C" sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n, double *out,
-                              void *stream) {
+extern "C" int64_t sd_reduction_scratch_bytes(void) { return kReductionScratchBytes; }
+
+namespace sd {
+// norm or inner product over 2^n amplitudes into buf[2 * kPartialSlots ...]
+// (width 1: norm of a; width 2: re, im of <a|b>), fixed summation order
+static sd_status launch_reduction(const void *a, const void *b, sd_dtype dtype, int32_t n, double *buf,
+                                  hipStream_t s) {
+    const int64_t dim = (int64_t)1 << n;
+    const int grid = (int)std::min<int64_t>(kPartialSlots, (dim + kBlock - 1) / kBlock);
+    if (!b) {
+        if (dtype == SD_C64)
+            hipLaunchKernelGGL(k_norm2<float2>, dim3(grid), dim3(kBlock), 0, s, (const float2 *)a, dim, buf);
+        else
+            hipLaunchKernelGGL(k_norm2<double2>, dim3(grid), dim3(kBlock), 0, s, (const double2 *)a, dim, buf);
+    } else if (dtype == SD_C64) {
+        hipLaunchKernelGGL(k_inner<float2>, dim3(grid), dim3(kBlock), 0, s, (const float2 *)a,
+                           (const float2 *)b, dim, buf);
+    } else {
+        hipLaunchKernelGGL(k_inner<double2>, dim3(grid), dim3(kBlock), 0, s, (const double2 *)a,
+                           (const double2 *)b, dim, buf);
+    }
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kFinalThreads), 0, s, buf, grid, b ? 2 : 1,
+                       buf + 2 * kPartialSlots);
+    return hip_check(hipGetLastError(), b ? "inner launch" : "norm2 launch");
+}
+}  // namespace sd
+
+extern "C" sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n, double *out, void *scratch,
+                              size_t scratch_bytes, void *stream) {
     if (!state || !out) return fail(SD_ERR_ARG, "sd_norm2: null argument");
     if (n < 0 || n > 40) return fail(SD_ERR_RANGE, "sd_norm2: n_qubits out of range");
     if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_norm2: bad dtype");
-    hipStream_t s = (hipStream_t)stream;
-    double *buf = nullptr;
-    sd_status r = red_scratch(&buf);
+    sd_status r = check_scratch(scratch, scratch_bytes, "sd_norm2");
     if (r != SD_OK) return r;
-    const int64_t dim = (int64_t)1 << n;
-    const int grid = (int)std::min<int64_t>(kPartialSlots, (dim + kBlock - 1) / kBlock);
-    if (dtype == SD_C64)
-        hipLaunchKernelGGL(k_norm2<float2>, dim3(grid), dim3(kBlock), 0, s, (const float2 *)state, dim, buf);
-    else
-        hipLaunchKernelGGL(k_norm2<double2>, dim3(grid), dim3(kBlock), 0, s, (const double2 *)state, dim, buf);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kFinalThreads), 0, s, buf, grid, 1, buf + 2 * kPartialSlots);
-    r = hip_check(hipGetLastError(), "norm2 launch");
+    hipStream_t s = (hipStream_t)stream;
+    double *buf = (double *)scratch;
+    r = launch_reduction(state, nullptr, dtype, n, buf, s);
     if (r != SD_OK) return r;
     r = hip_check(hipMemcpyAsync(out, buf + 2 * kPartialSlots, sizeof(double), hipMemcpyDeviceToHost, s),
                   "copy norm");
@@ -1498,24 +1511,15 @@ extern "C" sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n, doub
 }
 
 extern "C" sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int32_t n, double *out,
-                              void *stream) {
+                              void *scratch, size_t scratch_bytes, void *stream) {
     if (!a || !b || !out) return fail(SD_ERR_ARG, "sd_inner: null argument");
     if (n < 0 || n > 40) return fail(SD_ERR_RANGE, "sd_inner: n_qubits out of range");
     if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_inner: bad dtype");
-    hipStream_t s = (hipStream_t)stream;
-    double *buf = nullptr;
-    sd_status r = red_scratch(&buf);
+    sd_status r = check_scratch(scratch, scratch_bytes, "sd_inner");
     if (r != SD_OK) return r;
-    const int64_t dim = (int64_t)1 << n;
-    const int grid = (int)std::min<int64_t>(kPartialSlots, (dim + kBlock - 1) / kBlock);
-    if (dtype == SD_C64)
-        hipLaunchKernelGGL(k_inner<float2>, dim3(grid), dim3(kBlock), 0, s, (const float2 *)a,
-                           (const float2 *)b, dim, buf);
-    else
-        hipLaunchKernelGGL(k_inner<double2>, dim3(grid), dim3(kBlock), 0, s, (const double2 *)a,
-                           (const double2 *)b, dim, buf);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kFinalThreads), 0, s, buf, grid, 2, buf + 2 * kPartialSlots);
-    r = hip_check(hipGetLastError(), "inner launch");
+    hipStream_t s = (hipStream_t)stream;
+    double *buf = (double *)scratch;
+    r = launch_reduction(a, b, dtype, n, buf, s);
     if (r != SD_OK) return r;
     r = hip_check(hipMemcpyAsync(out, buf + 2 * kPartialSlots, 2 * sizeof(double),
                                  hipMemcpyDeviceToHost, s),
@@ -1530,41 +1534,79 @@ extern "C" sd_status sd_sync(void *stream) {
     return hip_check(hipGetLastError(), "sd_sync (async error)");
 }
 
+namespace sd {
+// the options of candidate i of an autotuning run
+static sd_plan_options autotune_options(const sd_plan_options &opt, sd_dtype dtype, int cand) {
+    sd_plan_options o = opt;
+    if (dtype == SD_C64) o.tile_log2_c64 = cand;
+    else o.tile_log2_c128 = cand;
+    if ((dtype == SD_C64 ? o.coalesce_log2_c64 : o.coalesce_log2_c128) >= cand) {
+        // (the coalescing default must stay below the tile)
+        if (dtype == SD_C64) o.coalesce_log2_c64 = std::min(4, cand - 1);
+        else o.coalesce_log2_c128 = std::min(3, cand - 1);
+    }
+    return o;
+}
+
+static sd_status autotune_check(const sd_hamiltonian *h, sd_dtype dtype, const int32_t *candidates,
+                                int32_t n_candidates) {
+    if (!h || !candidates || n_candidates < 1) return fail(SD_ERR_ARG, "sd_autotune: bad argument");
+    if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_autotune: bad dtype");
+    for (int i = 0; i < n_candidates; ++i)
+        if (candidates[i] < kMinTileLog2 || candidates[i] > kMaxTileLog2)
+            return fail(SD_ERR_RANGE, "sd_autotune: candidate tile size out of range");
+    return SD_OK;
+}
+}  // namespace sd
+
+extern "C" sd_status sd_autotune_workspace_bytes(const sd_hamiltonian *h, const sd_plan_options *base,
+                                                 sd_dtype dtype, const int32_t *candidates,
+                                                 int32_t n_candidates, int64_t *bytes) {
+    if (!bytes) return fail(SD_ERR_ARG, "sd_autotune_workspace_bytes: null argument");
+    sd_status r = autotune_check(h, dtype, candidates, n_candidates);
+    if (r != SD_OK) return r;
+    sd_plan_options opt;
+    sd_plan_options_default(&opt);
+    if (base) opt = *base;
+    int64_t most = 0;
+    for (int i = 0; i < n_candidates; ++i) {
+        const sd_plan_options o = autotune_options(opt, dtype, candidates[i]);
+        sd_plan_t *p = nullptr;
+        r = sd_plan(h, &o, &p);
+        if (r != SD_OK) return r;
+        most = std::max<int64_t>(most, p->ws_needed);
+        sd_plan_destroy(p);
+    }
+    *bytes = most;
+    return SD_OK;
+}
+
 extern "C" sd_status sd_autotune_tiles(const sd_hamiltonian *h, const sd_plan_options *base,
                                        sd_dtype dtype, void *state, double dt, int32_t order,
                                        int32_t steps, const int32_t *candidates, int32_t n_candidates,
+                                       void *workspace, size_t workspace_bytes,
                                        sd_plan_options *best, double *seconds, void *stream) {
-    if (!h || !state || !candidates || !best || n_candidates < 1 || steps < 1)
+    if (!state || !best || steps < 1 || !workspace)
         return fail(SD_ERR_ARG, "sd_autotune_tiles: bad argument");
-    if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_autotune_tiles: bad dtype");
-    for (int i = 0; i < n_candidates; ++i)
-        if (candidates[i] < kMinTileLog2 || candidates[i] > kMaxTileLog2)
-            return fail(SD_ERR_RANGE, "sd_autotune_tiles: candidate tile size out of range");
+    sd_status r = autotune_check(h, dtype, candidates, n_candidates);
+    if (r != SD_OK) return r;
     hipStream_t s = (hipStream_t)stream;
     sd_plan_options opt;
     sd_plan_options_default(&opt);
     if (base) opt = *base;
     double best_t = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    sd_status r = hip_check(hipEventCreate(&e0), "event");
+    r = hip_check(hipEventCreate(&e0), "event");
     if (r == SD_OK) r = hip_check(hipEventCreate(&e1), "event");
     for (int i = 0; i < n_candidates && r == SD_OK; ++i) {
-        sd_plan_options o = opt;
-        if (dtype == SD_C64) o.tile_log2_c64 = candidates[i];
-        else o.tile_log2_c128 = candidates[i];
-        if ((dtype == SD_C64 ? o.coalesce_log2_c64 : o.coalesce_log2_c128) >= candidates[i]) {
-            // (the coalescing default must stay below the tile)
-            if (dtype == SD_C64) o.coalesce_log2_c64 = std::min(4, candidates[i] - 1);
-            else o.coalesce_log2_c128 = std::min(3, candidates[i] - 1);
-        }
+        const sd_plan_options o = autotune_options(opt, dtype, candidates[i]);
         sd_plan_t *p = nullptr;
         r = sd_plan(h, &o, &p);
         if (r != SD_OK) break;
-        sd_plan_info info;
-        sd_plan_info_get(p, &info);
-        void *ws = nullptr;
-        r = hip_check(hipMalloc(&ws, (size_t)info.workspace_bytes), "autotune workspace");
-        if (r == SD_OK) r = sd_bind_workspace(p, ws, (size_t)info.workspace_bytes, stream);
+        // (a previous candidate's kernels may still read the workspace the
+        // new programs are uploaded into: sd_bind_workspace orders the upload
+        // on the same stream)
+        r = sd_bind_workspace(p, workspace, workspace_bytes, stream);
         if (r == SD_OK) r = sd_evolve(p, state, dtype, dt, 1, order, stream);
         if (r == SD_OK) r = hip_check(hipEventRecord(e0, s), "event record");
         if (r == SD_OK) r = sd_evolve(p, state, dtype, dt, steps, order, stream);
@@ -1572,10 +1614,6 @@ extern "C" sd_status sd_autotune_tiles(const sd_hamiltonian *h, const sd_plan_op
         if (r == SD_OK) r = hip_check(hipEventSynchronize(e1), "event sync");
         float ms = 0.f;
         if (r == SD_OK) r = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
-        if (ws) {
-            hipStreamSynchronize(s);
-            hipFree(ws);
-        }
         sd_plan_destroy(p);
         if (r != SD_OK) break;
         const double t = (double)ms / 1e3 / steps;

@@ -76,8 +76,8 @@ struct Row {
 };
 
 // Conjugation rules U P U^dagger of the tableau (Sec. "Tableau Representation",
-// gate table).  CNOT uses z_c ^= z_t (see DESIGN notes: the printed z-rule of
-// the CNOT row disagrees with the two-qubit table; the standard rule agrees).
+// gate table).  CNOT uses z_c ^= z_t: the printed z-rule of the CNOT row
+// disagrees with the two-qubit table, and the standard rule agrees with it.
 void apply_gate(Row &row, const Gate &g);
 
 struct SynthOptions {
@@ -211,6 +211,7 @@ struct sd_plan_s {
     int64_t ws_off_scratch = 0;        // reduction scratch
     int64_t ws_off_terms = 0;          // per-term expectations: partials, then results
     bool bound = false;
+    uint64_t bind_epoch = 0;           // incremented by every sd_bind_workspace
     // layer-by-layer and term-by-term execution
     int32_t mode = SD_MODE_TILES;
     std::vector<std::vector<sd::LayerOp>> layers;   // per group, one application

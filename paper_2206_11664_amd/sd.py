@@ -31,7 +31,8 @@ EXPORTED = [
     "sd_plan_destroy",
     "sd_bind_workspace", "sd_evolve", "sd_expectation", "sd_term_expectations", "sd_norm2", "sd_inner",
     "sd_ensemble_create", "sd_ensemble_workspace_bytes", "sd_ensemble_bind_workspace",
-    "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_autotune_tiles", "sd_status_string",
+    "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_autotune_workspace_bytes",
+    "sd_autotune_tiles", "sd_reduction_scratch_bytes", "sd_status_string",
     "sd_last_error", "sd_version",
 ]
 
@@ -124,17 +125,20 @@ def lib():
         "sd_evolve": (st, [vp, vp, ctypes.c_int, ctypes.c_double, i64, i32, vp]),
         "sd_expectation": (st, [vp, vp, ctypes.c_int, dp, vp]),
         "sd_term_expectations": (st, [vp, vp, ctypes.c_int, dp, vp]),
-        "sd_norm2": (st, [vp, ctypes.c_int, i32, dp, vp]),
-        "sd_inner": (st, [vp, vp, ctypes.c_int, i32, dp, vp]),
+        "sd_reduction_scratch_bytes": (i64, []),
+        "sd_norm2": (st, [vp, ctypes.c_int, i32, dp, vp, ctypes.c_size_t, vp]),
+        "sd_inner": (st, [vp, vp, ctypes.c_int, i32, dp, vp, ctypes.c_size_t, vp]),
         "sd_ensemble_create": (st, [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.POINTER(vp)]),
         "sd_ensemble_workspace_bytes": (st, [vp, ctypes.POINTER(i64)]),
         "sd_ensemble_bind_workspace": (st, [vp, vp, ctypes.c_size_t, vp]),
         "sd_ensemble_evolve": (st, [vp, ctypes.POINTER(vp), ctypes.c_double, i64, i32, vp]),
         "sd_ensemble_destroy": (None, [vp]),
         "sd_sync": (st, [vp]),
+        "sd_autotune_workspace_bytes": (st, [vp, ctypes.POINTER(sd_plan_options), ctypes.c_int,
+                                             ctypes.POINTER(i32), i32, ctypes.POINTER(i64)]),
         "sd_autotune_tiles": (st, [vp, ctypes.POINTER(sd_plan_options), ctypes.c_int, vp, ctypes.c_double,
-                                   i32, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(sd_plan_options),
-                                   dp, vp]),
+                                   i32, i32, ctypes.POINTER(i32), i32, vp, ctypes.c_size_t,
+                                   ctypes.POINTER(sd_plan_options), dp, vp]),
         "sd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "sd_last_error": (ctypes.c_char_p, []),
         "sd_version": (ctypes.c_char_p, []),
@@ -344,16 +348,39 @@ def sd_term_expectations(p: int, state, stream=None) -> np.ndarray:
     return out
 
 
-def sd_norm2(state, n_qubits: int, stream=None) -> float:
+_scratch = {}
+
+
+def reduction_scratch(device):
+    """A caller-owned scratch tensor for sd_norm2 / sd_inner on `device`
+    (allocated by torch once per device and kept)."""
+    import torch
+    dev = torch.device(device)
+    key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
+    buf = _scratch.get(key)
+    if buf is None:
+        buf = torch.empty(int(lib().sd_reduction_scratch_bytes()), dtype=torch.uint8, device=dev)
+        _scratch[key] = buf
+    return buf
+
+
+def sd_reduction_scratch_bytes() -> int:
+    return int(lib().sd_reduction_scratch_bytes())
+
+
+def sd_norm2(state, n_qubits: int, stream=None, scratch=None) -> float:
+    buf = scratch if scratch is not None else reduction_scratch(state.device)
     out = ctypes.c_double()
     _check(lib().sd_norm2(_dev_ptr(state), _dtype_of(state), n_qubits, ctypes.byref(out),
-                          _stream(stream)))
+                          _dev_ptr(buf), buf.numel() * buf.element_size(), _stream(stream)))
     return out.value
 
 
-def sd_inner(a, b, n_qubits: int, stream=None) -> complex:
+def sd_inner(a, b, n_qubits: int, stream=None, scratch=None) -> complex:
+    buf = scratch if scratch is not None else reduction_scratch(a.device)
     out = (ctypes.c_double * 2)()
-    _check(lib().sd_inner(_dev_ptr(a), _dev_ptr(b), _dtype_of(a), n_qubits, out, _stream(stream)))
+    _check(lib().sd_inner(_dev_ptr(a), _dev_ptr(b), _dtype_of(a), n_qubits, out,
+                          _dev_ptr(buf), buf.numel() * buf.element_size(), _stream(stream)))
     return complex(out[0], out[1])
 
 
@@ -391,16 +418,32 @@ def sd_sync(stream=None):
     _check(lib().sd_sync(_stream(stream)))
 
 
+def sd_autotune_workspace_bytes(h: int, dtype: int, candidates: Sequence[int],
+                                base: Optional[sd_plan_options] = None) -> int:
+    cand = (ctypes.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    b = ctypes.c_int64()
+    _check(lib().sd_autotune_workspace_bytes(h, ctypes.byref(base) if base is not None else None,
+                                             int(dtype), cand, len(candidates), ctypes.byref(b)))
+    return b.value
+
+
 def sd_autotune_tiles(h: int, dtype: int, state, dt: float, order: int, steps: int,
                       candidates: Sequence[int], base: Optional[sd_plan_options] = None,
-                      stream=None):
-    """Returns (options of the fastest candidate, per-step seconds of each)."""
+                      stream=None, workspace=None):
+    """Returns (options of the fastest candidate, per-step seconds of each).
+    workspace: a device tensor of at least sd_autotune_workspace_bytes bytes
+    (allocated here by torch when not given)."""
+    import torch
+    if workspace is None:
+        nbytes = sd_autotune_workspace_bytes(h, dtype, candidates, base)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=state.device)
     cand = (ctypes.c_int32 * len(candidates))(*[int(c) for c in candidates])
     best = sd_plan_options()
     secs = np.zeros(len(candidates))
     _check(lib().sd_autotune_tiles(h, ctypes.byref(base) if base is not None else None, int(dtype),
                                    _dev_ptr(state), float(dt), int(order), int(steps), cand,
-                                   len(candidates), ctypes.byref(best),
+                                   len(candidates), _dev_ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), ctypes.byref(best),
                                    secs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    _stream(stream)))
     return best, secs

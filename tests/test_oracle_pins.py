@@ -204,6 +204,48 @@ def test_energy_matches_dense():
     assert abs(e - ref) < 1e-12
 
 
+@pytest.mark.parametrize("n,seed", [(3, 11), (5, 12), (6, 13)])
+def test_term_expectations_match_dense(n, seed):
+    # <psi|P_k|psi> of every merged term against the dense Pauli matrix
+    # (Kronecker products of the 2x2 matrices), for input lists with exact
+    # duplicates (merged at the first occurrence), identity strings and
+    # strings with several Y factors (the i^{#Y} phase: a real expectation
+    # needs it); the results come back in merged-term order.
+    rng = np.random.default_rng(seed)
+    ps = rand_paulis(rng, n, 14)
+    ps += [ps[3], "I" * n, ps[0], "Y" * n, ps[7]]
+    cs = rng.normal(size=len(ps))
+    psi = workloads.random_state(n, seed + 100)
+    t = oracle.build_terms(n, ps, cs)
+    got = oracle.term_expectations(n, ps, cs, psi)
+    assert got.shape == (len(t.c),) and len(t.c) < len(ps)
+    first = {}
+    for i, p in enumerate(ps):
+        first.setdefault(p, i)
+    for k, src in enumerate(t.source):
+        s = ps[int(src)]
+        assert first[s] == int(src)
+        want = np.vdot(psi, dense.pauli_matrix(s) @ psi)
+        assert abs(want.imag) < 1e-12
+        assert abs(got[k] - want.real) < 1e-13, (k, s, got[k], want)
+    # identity term: <psi|psi> = 1
+    k_id = [k for k, src in enumerate(t.source) if ps[int(src)] == "I" * n][0]
+    assert abs(got[k_id] - 1.0) < 1e-13
+    # the coefficient-weighted sum is the energy, and both match the dense
+    # expectation of H (merged coefficients)
+    e_dense = np.vdot(psi, dense.hamiltonian(ps, cs) @ psi).real
+    assert abs(float(np.dot(t.c, got)) - e_dense) < 1e-12
+    assert abs(oracle.energy(n, ps, cs, psi) - e_dense) < 1e-12
+    # a basis state: every term with an X part has expectation 0, a Z string
+    # has (-1)^{popcount(x & zmask)}
+    x0 = int(rng.integers(1 << n))
+    b = workloads.basis_state(n, x0)
+    gb = oracle.term_expectations(n, ps, cs, b)
+    for k in range(len(t.c)):
+        want = 0.0 if int(t.x[k]) else (-1.0) ** bin(x0 & int(t.z[k])).count("1")
+        assert gb[k] == want
+
+
 def test_energy_conserved_by_single_group():
     ps = ["ZZII", "IZZI", "IIZZ", "ZIIZ"]
     cs = [0.3, -0.7, 1.1, 0.2]
