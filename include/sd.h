@@ -346,6 +346,22 @@ sd_status sd_norm2(const void *state, sd_dtype dtype, int32_t n_qubits,
 sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int32_t n_qubits,
                    double *out, void *scratch, size_t scratch_bytes, void *stream);
 
+/* sd_inner for callers that cannot allocate device memory at all (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same kernels and the same fixed summation order as sd_inner (equal
+   inputs give bit-identical results), with the per-block partial sums in a
+   library-owned static device array of 33,280 bytes instead of caller
+   scratch.  Every GPU the library runs on holds one such array until the
+   process ends; calls on one GPU share it, so calls that overlap on one GPU
+   (other streams or threads) race and must be serialised by the caller.
+   The call allocates nothing.  a, b: device arrays of 2^n_qubits amplitudes
+   of `dtype`; out: host, out[0] = re, out[1] = im of sum conj(a_x) b_x;
+   synchronises `stream`.  Errors: SD_ERR_ARG (null pointers, bad dtype),
+   SD_ERR_RANGE (n_qubits outside 0..40, or a device ordinal above 63),
+   SD_ERR_HIP. */
+sd_status sd_inner_noalloc(const void *a, const void *b, sd_dtype dtype, int32_t n_qubits,
+                           double *out, void *stream);
+
 /* Ensemble of independent instances (uneven sizes allowed), evolved together.
    plans: `count` plans, each with a bound workspace; states: host array of
    `count` device pointers.  One launch per pass level per step.

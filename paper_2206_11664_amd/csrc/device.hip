@@ -1528,6 +1528,63 @@ extern "C" sd_status sd_inner(const void *a, const void *b, sd_dtype dtype, int3
     return hip_check(hipStreamSynchronize(s), "sd_inner sync");
 }
 
+// ---------------------------------------------------------------------------
+// sd_inner_noalloc: sd_inner with its per-block partial sums in a file-scope
+// device array instead of caller scratch.  Each GPU holds its own copy of
+// the array; its device address is looked up once per device (on the first
+// call with that device current) and kept.  Calls on one GPU share the
+// array, so calls that overlap on one GPU (other streams, other threads)
+// race; the partials are written before they are read, nothing needs
+// clearing.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocSlots = (int)(kReductionScratchBytes / (int64_t)sizeof(double));
+static __device__ __align__(256) double scratch[kNoAllocSlots];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kNoAllocDevices] = {};  // by device ordinal; null = not looked up yet
+
+sd_status noalloc_scratch(double **out) {
+    int dev = -1;
+    sd_status r = hip_check(hipGetDevice(&dev), "sd_inner_noalloc: hipGetDevice");
+    if (r != SD_OK) return r;
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(SD_ERR_RANGE, "sd_inner_noalloc: device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        r = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)),
+                      "sd_inner_noalloc: hipGetSymbolAddress(scratch)");
+        if (r != SD_OK) return r;
+        if (!ptr) return fail(SD_ERR_HIP, "sd_inner_noalloc: null address for the static scratch");
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return SD_OK;
+}
+}  // namespace
+
+extern "C" sd_status sd_inner_noalloc(const void *a, const void *b, sd_dtype dtype, int32_t n,
+                                      double *out, void *stream) {
+    if (!a || !b || !out) return fail(SD_ERR_ARG, "sd_inner_noalloc: null argument");
+    if (n < 0 || n > 40)
+        return fail(SD_ERR_RANGE, "sd_inner_noalloc: n_qubits " + std::to_string(n) +
+                                      " outside 0..40");
+    if (dtype != SD_C64 && dtype != SD_C128) return fail(SD_ERR_ARG, "sd_inner_noalloc: bad dtype");
+    double *buf = nullptr;
+    sd_status r = noalloc_scratch(&buf);
+    if (r != SD_OK) return r;
+    static_assert(2 * kPartialSlots + 2 <= kNoAllocSlots, "static scratch too small");
+    hipStream_t s = (hipStream_t)stream;
+    r = launch_reduction(a, b, dtype, n, buf, s);
+    if (r != SD_OK) return r;
+    r = hip_check(hipMemcpyAsync(out, buf + 2 * kPartialSlots, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, s),
+                  "sd_inner_noalloc: copy result");
+    if (r != SD_OK) return r;
+    return hip_check(hipStreamSynchronize(s), "sd_inner_noalloc sync");
+}
+
 extern "C" sd_status sd_sync(void *stream) {
     sd_status r = hip_check(hipStreamSynchronize((hipStream_t)stream), "sd_sync");
     if (r != SD_OK) return r;

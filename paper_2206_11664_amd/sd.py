@@ -30,6 +30,7 @@ EXPORTED = [
     "sd_plan_export_group", "sd_plan_pass_count", "sd_plan_export_pass", "sd_plan_export_rounds",
     "sd_plan_destroy",
     "sd_bind_workspace", "sd_evolve", "sd_expectation", "sd_term_expectations", "sd_norm2", "sd_inner",
+    "sd_inner_noalloc",
     "sd_ensemble_create", "sd_ensemble_workspace_bytes", "sd_ensemble_bind_workspace",
     "sd_ensemble_evolve", "sd_ensemble_destroy", "sd_sync", "sd_autotune_workspace_bytes",
     "sd_autotune_tiles", "sd_reduction_scratch_bytes", "sd_status_string",
@@ -128,6 +129,7 @@ def lib():
         "sd_reduction_scratch_bytes": (i64, []),
         "sd_norm2": (st, [vp, ctypes.c_int, i32, dp, vp, ctypes.c_size_t, vp]),
         "sd_inner": (st, [vp, vp, ctypes.c_int, i32, dp, vp, ctypes.c_size_t, vp]),
+        "sd_inner_noalloc": (st, [vp, vp, ctypes.c_int, i32, dp, vp]),
         "sd_ensemble_create": (st, [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.POINTER(vp)]),
         "sd_ensemble_workspace_bytes": (st, [vp, ctypes.POINTER(i64)]),
         "sd_ensemble_bind_workspace": (st, [vp, vp, ctypes.c_size_t, vp]),
@@ -381,6 +383,14 @@ def sd_inner(a, b, n_qubits: int, stream=None, scratch=None) -> complex:
     out = (ctypes.c_double * 2)()
     _check(lib().sd_inner(_dev_ptr(a), _dev_ptr(b), _dtype_of(a), n_qubits, out,
                           _dev_ptr(buf), buf.numel() * buf.element_size(), _stream(stream)))
+    return complex(out[0], out[1])
+
+
+def sd_inner_noalloc(a, b, n_qubits: int, stream=None) -> complex:
+    """sd_inner with the library's static device scratch (no caller memory)."""
+    out = (ctypes.c_double * 2)()
+    _check(lib().sd_inner_noalloc(_dev_ptr(a), _dev_ptr(b), _dtype_of(a), n_qubits, out,
+                                  _stream(stream)))
     return complex(out[0], out[1])
 
 

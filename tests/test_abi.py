@@ -79,6 +79,12 @@ def test_reductions_and_autotune_validate_caller_memory_without_device():
     assert L.sd_inner(8, 16, 1, 10, out, 256, 16, None) == sd.SD_ERR_WORKSPACE
     assert L.sd_norm2(8, 0, 41, out, 256, need, None) == sd.SD_ERR_RANGE
     assert L.sd_inner(8, 16, 5, 10, out, 256, need, None) == sd.SD_ERR_ARG   # dtype
+    # the variant with the library's static scratch: the same argument checks
+    assert L.sd_inner_noalloc(None, 16, 1, 10, out, None) == sd.SD_ERR_ARG
+    assert L.sd_inner_noalloc(8, 16, 1, 10, None, None) == sd.SD_ERR_ARG
+    assert L.sd_inner_noalloc(8, 16, 1, 41, out, None) == sd.SD_ERR_RANGE
+    assert L.sd_inner_noalloc(8, 16, 1, -1, out, None) == sd.SD_ERR_RANGE
+    assert L.sd_inner_noalloc(8, 16, 5, 10, out, None) == sd.SD_ERR_ARG   # dtype
     # the autotuner's workspace: the largest plan workspace among the candidates
     h = sd.sd_hamiltonian_create(6, ["XXIIII", "ZZIIII", "IXXIII", "IIIZZZ"], [1.0, 0.5, 0.2, 0.3])
     ws = sd.sd_autotune_workspace_bytes(h, sd.SD_C64, [6, 7, 8])
