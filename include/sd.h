@@ -124,6 +124,14 @@ typedef struct {
        SD_MODE_TERMWISE: one Pauli-rotation pass per term (Eq. trotter_decomp,
          the paper's baseline), in the same group order. */
     int32_t mode;
+    /* complex64: the fewest contiguous low bits a group's passes may fall
+       back to (at most two below coalesce_log2_c64) where that needs fewer
+       passes and the planner's cost model finds it cheaper: each fewer
+       pass is one fewer HBM round trip and one fewer complex64 rounding of
+       every amplitude.  Default 2 (32-byte runs); a value of at least
+       coalesce_log2_c64 keeps every pass at that width; negative values
+       are SD_ERR_RANGE. */
+    int32_t coalesce_min_log2_c64;
 } sd_plan_options;
 
 enum { SD_MODE_TILES = 0, SD_MODE_PAPER_LAYERS = 1, SD_MODE_TERMWISE = 2 };
@@ -368,7 +376,10 @@ sd_status sd_inner_noalloc(const void *a, const void *b, sd_dtype dtype, int32_t
    sd_ensemble_workspace_bytes: the device bytes for the per-level segment
    tables, enough for every order (1, 2, 4); the caller allocates them
    (256-byte aligned) and binds them with sd_ensemble_bind_workspace before
-   sd_ensemble_evolve (SD_ERR_WORKSPACE otherwise). */
+   sd_ensemble_evolve (SD_ERR_WORKSPACE otherwise).  The ensemble keeps
+   pointers to the plans, which must outlive it; a plan may be rebound to
+   another workspace between calls (the next sd_ensemble_evolve rebuilds
+   its step tables, as it does for other state pointers, dt or order). */
 sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t count,
                              sd_dtype dtype, sd_ensemble **out);
 sd_status sd_ensemble_workspace_bytes(const sd_ensemble *e, int64_t *bytes);

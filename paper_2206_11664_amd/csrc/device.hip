@@ -674,7 +674,26 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
     // Offsets are in bytes from the state pointer.
     T pre[kE];
     const char *sbase = (const char *)state;
+    // Tiles that differ only in free bits below the 128-byte line share every
+    // line they touch (a pass with fewer than log2(128 / sizeof(T)) contiguous
+    // low bits).  The block then takes them one after the other: iteration k
+    // of block b (tile t0 + k * stride of the loop) runs tile
+    // ((k >> s) * stride + b) * 2^s + (k mod 2^s), a bijection of the tile
+    // range when stride * 2^s divides it, so that a line fetched for one tile
+    // is still in the cache for its partners, and their partial-line stores
+    // meet in the cache.  Strided launches only (a contiguous range already
+    // runs partners in a row).
+    int sh = 0;
+    if (stride > 1) {
+        const int line_bits = sizeof(T) == 8 ? 4 : 3;
+        while (sh < pd.n_free && pd.free_pos[sh] < line_bits) ++sh;
+        if (t1 % (stride << sh) != 0 || t0 >= stride) sh = 0;
+    }
     auto tile_off = [&](int64_t ti) {
+        if (sh) {
+            const int64_t k = (ti - t0) / stride;
+            ti = (((k >> sh) * stride + t0) << sh) | (k & ((1 << sh) - 1));
+        }
         uint64_t xT = 0;
         for (int i = 0; i < pd.n_free; ++i)
             if ((ti >> i) & 1) xT |= (uint64_t)1 << pd.free_pos[i];
@@ -1710,6 +1729,7 @@ struct sd_ensemble {
     double g_dt = 0;
     int g_order = 0;
     std::vector<void *> g_states;
+    std::vector<const void *> g_plan_ws;  // each plan's workspace when the graph was built
     std::vector<int> g_small;   // instances run through sd_evolve each step
     ~sd_ensemble() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1887,7 +1907,13 @@ extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, dou
         if (r != SD_OK) return r;
     }
     std::vector<void *> st(states, states + e->plans.size());
-    if (!(e->exec && e->g_dt == dt && e->g_order == order && e->g_states == st)) {
+    // The captured step holds every plan's workspace addresses (its pass
+    // records and term tables): a plan rebound to other memory since then
+    // invalidates it, like new state pointers or another dt or order.
+    std::vector<const void *> pws(e->plans.size());
+    for (size_t i = 0; i < e->plans.size(); ++i) pws[i] = e->plans[i]->ws;
+    if (!(e->exec && e->g_dt == dt && e->g_order == order && e->g_states == st &&
+          e->g_plan_ws == pws)) {
         if (e->exec) {
             (void)hipGraphExecDestroy(e->exec);
             e->exec = nullptr;
@@ -1919,6 +1945,7 @@ extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, dou
         e->g_dt = dt;
         e->g_order = order;
         e->g_states = st;
+        e->g_plan_ws = pws;
     }
     r = hip_check(hipEventRecord(e->ev_in, user), "event record");
     if (r != SD_OK) return r;

@@ -1,4 +1,5 @@
 // sd_plan: grouping, per-group Clifford synthesis, device program compile.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -16,6 +17,7 @@ extern "C" void sd_plan_options_default(sd_plan_options *o) {
     o->coalesce_log2_c64 = 4;
     o->coalesce_log2_c128 = 3;
     o->mode = SD_MODE_TILES;
+    o->coalesce_min_log2_c64 = 2;
 }
 
 namespace {
@@ -62,7 +64,7 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
         !chk(opt.tile_log2_c128, kMinTileLog2, kMaxTileLog2) ||
         !chk(opt.coalesce_log2_c64, 0, 6) || !chk(opt.coalesce_log2_c128, 0, 6) ||
         opt.coalesce_log2_c64 >= opt.tile_log2_c64 ||
-        opt.coalesce_log2_c128 >= opt.tile_log2_c128)
+        opt.coalesce_log2_c128 >= opt.tile_log2_c128 || opt.coalesce_min_log2_c64 < 0)
         return fail(SD_ERR_RANGE, "sd_plan: tile/coalescing options out of range");
     if (opt.mode != SD_MODE_TILES && opt.mode != SD_MODE_PAPER_LAYERS && opt.mode != SD_MODE_TERMWISE)
         return fail(SD_ERR_ARG, "sd_plan: unknown mode");
@@ -101,10 +103,12 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
     build_layers(*p);
 
     sd_status st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c64,
-                                   opt.coalesce_log2_c64, &p->prog[SD_C64], true);
+                                   opt.coalesce_log2_c64,
+                                   std::min(opt.coalesce_min_log2_c64, opt.coalesce_log2_c64),
+                                   &p->prog[SD_C64], true);
     if (st == SD_OK)
         st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c128,
-                             opt.coalesce_log2_c128, &p->prog[SD_C128], false);
+                             opt.coalesce_log2_c128, opt.coalesce_log2_c128, &p->prog[SD_C128], false);
     if (st != SD_OK) {
         delete p;
         return st;

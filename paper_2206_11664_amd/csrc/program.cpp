@@ -816,13 +816,19 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
 // Splits of a group into sub-groups are compared by the sum over their passes.
 constexpr int kShrinkMaxTerms = 32;  // passes with more Lambda terms keep the full tile
 
+// Extra modelled time per pass of a tile with one or two fewer contiguous low
+// bits than the 128-byte line (fitted: 64-byte runs cost about 130, 32-byte
+// runs about 370 per pass on the benchmark, with partner tiles run in a row).
+constexpr int64_t kCoalescePenalty1 = 130;
+constexpr int64_t kCoalescePenalty2 = 370;
+
 static int64_t pass_cost(int rho) {
     return 500 + 280 * ((std::max(rho, 1) + kChunkBits - 1) / kChunkBits) + 39 * (int64_t)rho;
 }
 
 sd_status compile_program(int n, const std::vector<Term> &T,
                           const std::vector<std::vector<int64_t>> &groups,
-                          int D_max, int c, Program *out, bool shrink) {
+                          int D_max, int c, int c_min, Program *out, bool shrink) {
     Program &P = *out;
     P.D_max = D_max;
     P.c = c;
@@ -840,219 +846,246 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         // (pass_cost of each sub-group's X rank) is kept, and then sub-groups
         // are dissolved into the others while that lowers the cost.  Every
         // split is exact: the terms commute.
-        auto grow = [&](uint64_t seed) {
-            std::vector<std::vector<int64_t>> subs;
-            std::vector<int64_t> rest(groups[g].begin(), groups[g].end());
-            uint64_t rng = seed;
-            auto next = [&]() {
-                rng ^= rng << 13;
-                rng ^= rng >> 7;
-                rng ^= rng << 17;
-                return rng;
-            };
-            while (!rest.empty()) {
-                Echelon span;
-                for (int q = 0; q < cc; ++q) span.insert(1ull << q);
-                std::vector<int64_t> cur;
-                while (true) {
-                    std::vector<int64_t> keep;
-                    for (int64_t k : rest) {
-                        if ((int)cur.size() < kMaxPassTerms && span.contains(T[k].x))
-                            cur.push_back(k);
-                        else
-                            keep.push_back(k);
-                    }
-                    rest.swap(keep);
-                    if (rest.empty() || span.dim() >= Dcap || (int)cur.size() >= kMaxPassTerms) break;
-                    // Adding x_a brings in exactly the terms whose X part has
-                    // the same remainder modulo the span (the echelon basis is
-                    // fully reduced, so the remainder is the coset's unique
-                    // representative): the score is a count of equal remainders.
-                    std::vector<uint64_t> rem(rest.size());
-                    std::unordered_map<uint64_t, int> count;
-                    for (size_t a = 0; a < rest.size(); ++a) {
-                        rem[a] = span.reduce(T[rest[a]].x);
-                        ++count[rem[a]];
-                    }
-                    size_t best = 0, second = 0;
-                    int best_score = -1, second_score = -1;
-                    for (size_t a = 0; a < rest.size(); ++a) {
-                        const int score = count[rem[a]];
-                        // (seed 0: the plain greedy, first best in term order)
-                        const bool tie = seed && score == best_score && (next() & 1);
-                        if (score > best_score || tie) {
-                            second = best;
-                            second_score = best_score;
-                            best_score = score;
-                            best = a;
-                        } else if (score > second_score) {
-                            second_score = score;
-                            second = a;
+        // the split of group g for a tile space with cc contiguous low bits,
+        // and its modelled cost
+        auto split_group = [&](const int cc) {
+            auto grow = [&](uint64_t seed) {
+                std::vector<std::vector<int64_t>> subs;
+                std::vector<int64_t> rest(groups[g].begin(), groups[g].end());
+                uint64_t rng = seed;
+                auto next = [&]() {
+                    rng ^= rng << 13;
+                    rng ^= rng >> 7;
+                    rng ^= rng << 17;
+                    return rng;
+                };
+                while (!rest.empty()) {
+                    Echelon span;
+                    for (int q = 0; q < cc; ++q) span.insert(1ull << q);
+                    std::vector<int64_t> cur;
+                    while (true) {
+                        std::vector<int64_t> keep;
+                        for (int64_t k : rest) {
+                            if ((int)cur.size() < kMaxPassTerms && span.contains(T[k].x))
+                                cur.push_back(k);
+                            else
+                                keep.push_back(k);
                         }
+                        rest.swap(keep);
+                        if (rest.empty() || span.dim() >= Dcap || (int)cur.size() >= kMaxPassTerms) break;
+                        // Adding x_a brings in exactly the terms whose X part has
+                        // the same remainder modulo the span (the echelon basis is
+                        // fully reduced, so the remainder is the coset's unique
+                        // representative): the score is a count of equal remainders.
+                        std::vector<uint64_t> rem(rest.size());
+                        std::unordered_map<uint64_t, int> count;
+                        for (size_t a = 0; a < rest.size(); ++a) {
+                            rem[a] = span.reduce(T[rest[a]].x);
+                            ++count[rem[a]];
+                        }
+                        size_t best = 0, second = 0;
+                        int best_score = -1, second_score = -1;
+                        for (size_t a = 0; a < rest.size(); ++a) {
+                            const int score = count[rem[a]];
+                            // (seed 0: the plain greedy, first best in term order)
+                            const bool tie = seed && score == best_score && (next() & 1);
+                            if (score > best_score || tie) {
+                                second = best;
+                                second_score = best_score;
+                                best_score = score;
+                                best = a;
+                            } else if (score > second_score) {
+                                second_score = score;
+                                second = a;
+                            }
+                        }
+                        if (seed && second_score >= 0 && (next() % 8) == 0) best = second;
+                        span.insert(T[rest[best]].x);
+                        cur.push_back(rest[best]);
+                        rest.erase(rest.begin() + (long)best);
                     }
-                    if (seed && second_score >= 0 && (next() % 8) == 0) best = second;
-                    span.insert(T[rest[best]].x);
-                    cur.push_back(rest[best]);
-                    rest.erase(rest.begin() + (long)best);
+                    subs.push_back(std::move(cur));
                 }
-                subs.push_back(std::move(cur));
-            }
-            return subs;
-        };
-        // a sub-group under construction: its tile space (low bits and X
-        // parts), the rank of its X parts alone, its terms
-        struct Sub {
-            Echelon tile, xs;
-            std::vector<int64_t> terms;
-        };
-        auto make_sub = [&](const std::vector<int64_t> &terms) {
-            Sub u;
-            for (int q = 0; q < cc; ++q) u.tile.insert(1ull << q);
-            for (int64_t k : terms) {
-                u.tile.insert(T[k].x);
-                u.xs.insert(T[k].x);
-            }
-            u.terms = terms;
-            return u;
-        };
-        auto split_cost = [&](const std::vector<std::vector<int64_t>> &subs) {
-            int64_t cost = 0;
-            for (auto &t : subs) {
-                Echelon xs;
-                for (int64_t k : t) xs.insert(T[k].x);
-                cost += pass_cost(xs.dim());
-            }
-            return cost;
-        };
-        std::vector<std::vector<int64_t>> best_split = grow(0);
-        int64_t best_cost = split_cost(best_split);
-        // (no restarts when the plain greedy meets the bound set by the
-        // dimension of the group's X span with the low bits)
-        size_t lb = 1;
-        {
-            Echelon all;
-            for (int q = 0; q < cc; ++q) all.insert(1ull << q);
-            for (int64_t k : groups[g]) all.insert(T[k].x);
-            const int room = std::max(1, Dcap - cc);
-            lb = (size_t)std::max(1, (all.dim() - cc + room - 1) / room);
-        }
-        // (each restart costs about size^2 reductions: fewer for big groups)
-        const size_t gs = groups[g].size();
-        const uint64_t restarts = std::max<uint64_t>(4, std::min<uint64_t>(48, 40000 / (gs * gs + 1)));
-        for (uint64_t r = 1; r <= restarts && gs > 1 && best_split.size() > lb; ++r) {
-            auto cand = grow(0x9e3779b97f4a7c15ull * r + g * 0x632be59bd9b4e019ull + 1);
-            const int64_t cost = split_cost(cand);
-            if (cost < best_cost) {
-                best_split = std::move(cand);
-                best_cost = cost;
-            }
-        }
-        // Dissolve sub-groups, smallest first: each of its terms goes to the
-        // other sub-group where it adds the least modelled cost (within the
-        // tile space and term limits); kept when every term finds a place and
-        // the total cost drops.
-        if (best_split.size() > 1) {
-            std::vector<Sub> cur;
-            for (auto &t : best_split) cur.push_back(make_sub(t));
-            auto total = [&](const std::vector<Sub> &v) {
+                return subs;
+            };
+            // a sub-group under construction: its tile space (low bits and X
+            // parts), the rank of its X parts alone, its terms
+            struct Sub {
+                Echelon tile, xs;
+                std::vector<int64_t> terms;
+            };
+            auto make_sub = [&](const std::vector<int64_t> &terms) {
+                Sub u;
+                for (int q = 0; q < cc; ++q) u.tile.insert(1ull << q);
+                for (int64_t k : terms) {
+                    u.tile.insert(T[k].x);
+                    u.xs.insert(T[k].x);
+                }
+                u.terms = terms;
+                return u;
+            };
+            auto split_cost = [&](const std::vector<std::vector<int64_t>> &subs) {
                 int64_t cost = 0;
-                for (auto &u : v) cost += pass_cost(u.xs.dim());
+                for (auto &t : subs) {
+                    Echelon xs;
+                    for (int64_t k : t) xs.insert(T[k].x);
+                    cost += pass_cost(xs.dim());
+                }
                 return cost;
             };
-            // (the two moves alternate until neither lowers the cost: each
-            // accepted move lowers it, so this ends)
-            for (bool again = true; again;) {
-                again = false;
-                for (bool improved = true; improved && cur.size() > 1;) {
-                    improved = false;
-                    std::vector<size_t> order(cur.size());
-                    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-                    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-                        return cur[a].terms.size() < cur[b].terms.size();
-                    });
-                    const int64_t before = total(cur);
-                    for (size_t sidx : order) {
-                        std::vector<Sub> trial = cur;
-                        bool placed = true;
-                        for (int64_t k : cur[sidx].terms) {
-                            const uint64_t x = T[k].x;
-                            size_t to = SIZE_MAX;
-                            int64_t delta_best = INT64_MAX;
-                            for (size_t j = 0; j < trial.size(); ++j) {
-                                if (j == sidx || (int)trial[j].terms.size() >= kMaxPassTerms) continue;
-                                if (!trial[j].tile.contains(x) && trial[j].tile.dim() >= Dcap) continue;
-                                const int rho = trial[j].xs.dim();
-                                const int rho_new = rho + (trial[j].xs.contains(x) ? 0 : 1);
-                                const int64_t delta = pass_cost(rho_new) - pass_cost(rho);
-                                if (delta < delta_best) {
-                                    delta_best = delta;
-                                    to = j;
-                                }
-                            }
-                            if (to == SIZE_MAX) {
-                                placed = false;
-                                break;
-                            }
-                            trial[to].tile.insert(x);
-                            trial[to].xs.insert(x);
-                            trial[to].terms.push_back(k);
-                        }
-                        if (!placed) continue;
-                        trial.erase(trial.begin() + (long)sidx);
-                        if (total(trial) < before) {
-                            cur = std::move(trial);
-                            improved = true;
-                            break;
-                        }
-                    }
-                }
-                // Move single terms: a term whose X part lies outside the span of
-                // the rest of its sub-group moves to another sub-group when that
-                // lowers the cost (e.g. a span of 13 = 3 rounds drops to 12 = 2).
-                for (bool improved = true; improved && cur.size() > 1;) {
-                    improved = false;
-                    for (size_t sidx = 0; sidx < cur.size() && !improved; ++sidx) {
-                        const int rho_s = cur[sidx].xs.dim();
-                        const auto &ts = cur[sidx].terms;
-                        // (a lone term is never moved: that would leave an empty
-                        // sub-group; dissolving above covers that case)
-                        if (ts.size() < 2) continue;
-                        for (size_t ti = 0; ti < ts.size() && !improved; ++ti) {
-                            const uint64_t x = T[ts[ti]].x;
-                            Echelon wo;
-                            for (size_t u = 0; u < ts.size(); ++u)
-                                if (u != ti) wo.insert(T[ts[u]].x);
-                            if (wo.contains(x)) continue;  // its X part is spanned by the rest
-                            const int64_t gain_s = pass_cost(rho_s) - pass_cost(wo.dim());
-                            size_t to = SIZE_MAX;
-                            int64_t best_delta = 0;
-                            for (size_t j = 0; j < cur.size(); ++j) {
-                                if (j == sidx || (int)cur[j].terms.size() >= kMaxPassTerms) continue;
-                                if (!cur[j].tile.contains(x) && cur[j].tile.dim() >= Dcap) continue;
-                                const int rho = cur[j].xs.dim();
-                                const int rho_new = rho + (cur[j].xs.contains(x) ? 0 : 1);
-                                const int64_t delta = pass_cost(rho_new) - pass_cost(rho) - gain_s;
-                                if (delta < best_delta) {
-                                    best_delta = delta;
-                                    to = j;
-                                }
-                            }
-                            if (to == SIZE_MAX) continue;
-                            const int64_t k = ts[ti];
-                            std::vector<int64_t> rest_terms;
-                            for (size_t u = 0; u < ts.size(); ++u)
-                                if (u != ti) rest_terms.push_back(ts[u]);
-                            cur[to].tile.insert(x);
-                            cur[to].xs.insert(x);
-                            cur[to].terms.push_back(k);
-                            cur[sidx] = make_sub(rest_terms);
-                            improved = again = true;
-                        }
-                    }
+            std::vector<std::vector<int64_t>> best_split = grow(0);
+            int64_t best_cost = split_cost(best_split);
+            // (no restarts when the plain greedy meets the bound set by the
+            // dimension of the group's X span with the low bits)
+            size_t lb = 1;
+            {
+                Echelon all;
+                for (int q = 0; q < cc; ++q) all.insert(1ull << q);
+                for (int64_t k : groups[g]) all.insert(T[k].x);
+                const int room = std::max(1, Dcap - cc);
+                lb = (size_t)std::max(1, (all.dim() - cc + room - 1) / room);
+            }
+            // (each restart costs about size^2 reductions: fewer for big groups)
+            const size_t gs = groups[g].size();
+            const uint64_t restarts = std::max<uint64_t>(4, std::min<uint64_t>(48, 40000 / (gs * gs + 1)));
+            for (uint64_t r = 1; r <= restarts && gs > 1 && best_split.size() > lb; ++r) {
+                auto cand = grow(0x9e3779b97f4a7c15ull * r + g * 0x632be59bd9b4e019ull + 1);
+                const int64_t cost = split_cost(cand);
+                if (cost < best_cost) {
+                    best_split = std::move(cand);
+                    best_cost = cost;
                 }
             }
-            best_split.clear();
-            for (auto &u : cur) best_split.push_back(std::move(u.terms));
+            // Dissolve sub-groups, smallest first: each of its terms goes to the
+            // other sub-group where it adds the least modelled cost (within the
+            // tile space and term limits); kept when every term finds a place and
+            // the total cost drops.
+            if (best_split.size() > 1) {
+                std::vector<Sub> cur;
+                for (auto &t : best_split) cur.push_back(make_sub(t));
+                auto total = [&](const std::vector<Sub> &v) {
+                    int64_t cost = 0;
+                    for (auto &u : v) cost += pass_cost(u.xs.dim());
+                    return cost;
+                };
+                // (the two moves alternate until neither lowers the cost: each
+                // accepted move lowers it, so this ends)
+                for (bool again = true; again;) {
+                    again = false;
+                    for (bool improved = true; improved && cur.size() > 1;) {
+                        improved = false;
+                        std::vector<size_t> order(cur.size());
+                        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+                        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+                            return cur[a].terms.size() < cur[b].terms.size();
+                        });
+                        const int64_t before = total(cur);
+                        for (size_t sidx : order) {
+                            std::vector<Sub> trial = cur;
+                            bool placed = true;
+                            for (int64_t k : cur[sidx].terms) {
+                                const uint64_t x = T[k].x;
+                                size_t to = SIZE_MAX;
+                                int64_t delta_best = INT64_MAX;
+                                for (size_t j = 0; j < trial.size(); ++j) {
+                                    if (j == sidx || (int)trial[j].terms.size() >= kMaxPassTerms) continue;
+                                    if (!trial[j].tile.contains(x) && trial[j].tile.dim() >= Dcap) continue;
+                                    const int rho = trial[j].xs.dim();
+                                    const int rho_new = rho + (trial[j].xs.contains(x) ? 0 : 1);
+                                    const int64_t delta = pass_cost(rho_new) - pass_cost(rho);
+                                    if (delta < delta_best) {
+                                        delta_best = delta;
+                                        to = j;
+                                    }
+                                }
+                                if (to == SIZE_MAX) {
+                                    placed = false;
+                                    break;
+                                }
+                                trial[to].tile.insert(x);
+                                trial[to].xs.insert(x);
+                                trial[to].terms.push_back(k);
+                            }
+                            if (!placed) continue;
+                            trial.erase(trial.begin() + (long)sidx);
+                            if (total(trial) < before) {
+                                cur = std::move(trial);
+                                improved = true;
+                                break;
+                            }
+                        }
+                    }
+                    // Move single terms: a term whose X part lies outside the span of
+                    // the rest of its sub-group moves to another sub-group when that
+                    // lowers the cost (e.g. a span of 13 = 3 rounds drops to 12 = 2).
+                    for (bool improved = true; improved && cur.size() > 1;) {
+                        improved = false;
+                        for (size_t sidx = 0; sidx < cur.size() && !improved; ++sidx) {
+                            const int rho_s = cur[sidx].xs.dim();
+                            const auto &ts = cur[sidx].terms;
+                            // (a lone term is never moved: that would leave an empty
+                            // sub-group; dissolving above covers that case)
+                            if (ts.size() < 2) continue;
+                            for (size_t ti = 0; ti < ts.size() && !improved; ++ti) {
+                                const uint64_t x = T[ts[ti]].x;
+                                Echelon wo;
+                                for (size_t u = 0; u < ts.size(); ++u)
+                                    if (u != ti) wo.insert(T[ts[u]].x);
+                                if (wo.contains(x)) continue;  // its X part is spanned by the rest
+                                const int64_t gain_s = pass_cost(rho_s) - pass_cost(wo.dim());
+                                size_t to = SIZE_MAX;
+                                int64_t best_delta = 0;
+                                for (size_t j = 0; j < cur.size(); ++j) {
+                                    if (j == sidx || (int)cur[j].terms.size() >= kMaxPassTerms) continue;
+                                    if (!cur[j].tile.contains(x) && cur[j].tile.dim() >= Dcap) continue;
+                                    const int rho = cur[j].xs.dim();
+                                    const int rho_new = rho + (cur[j].xs.contains(x) ? 0 : 1);
+                                    const int64_t delta = pass_cost(rho_new) - pass_cost(rho) - gain_s;
+                                    if (delta < best_delta) {
+                                        best_delta = delta;
+                                        to = j;
+                                    }
+                                }
+                                if (to == SIZE_MAX) continue;
+                                const int64_t k = ts[ti];
+                                std::vector<int64_t> rest_terms;
+                                for (size_t u = 0; u < ts.size(); ++u)
+                                    if (u != ti) rest_terms.push_back(ts[u]);
+                                cur[to].tile.insert(x);
+                                cur[to].xs.insert(x);
+                                cur[to].terms.push_back(k);
+                                cur[sidx] = make_sub(rest_terms);
+                                improved = again = true;
+                            }
+                        }
+                    }
+                }
+                best_split.clear();
+                for (auto &u : cur) best_split.push_back(std::move(u.terms));
+            }
+            return std::make_pair(best_split, split_cost(best_split));
+        };
+        // complex64: passes may take fewer contiguous low bits (down to
+        // c_min) where that needs fewer passes: each HBM access run is then
+        // shorter (64 or 32 bytes), which the tile order of the kernels
+        // recovers only in part (kCoalescePenalty per pass), so the width of
+        // least modelled cost is taken per group.
+        int cg = cc;
+        std::vector<std::vector<int64_t>> best_split;
+        {
+            auto r = split_group(cc);
+            int64_t best_total = r.second;
+            best_split = std::move(r.first);
+            for (int c2 = cc - 1; c2 >= std::max(0, c_min) && c2 >= cc - 2; --c2) {
+                auto r2 = split_group(c2);
+                const int64_t pen = (cc - c2 == 1 ? kCoalescePenalty1 : kCoalescePenalty2) *
+                                    (int64_t)r2.first.size();
+                if (r2.second + pen < best_total) {
+                    best_total = r2.second + pen;
+                    best_split = std::move(r2.first);
+                    cg = c2;
+                }
+            }
         }
         std::vector<std::vector<int64_t>> &subs = best_split;
         for (auto &s : subs) {
@@ -1065,11 +1098,11 @@ sd_status compile_program(int n, const std::vector<Term> &T,
             int Dt = Dcap;
             if (shrink && (int)s.size() <= kShrinkMaxTerms) {
                 Echelon sp;
-                for (int q = 0; q < cc; ++q) sp.insert(1ull << q);
+                for (int q = 0; q < cg; ++q) sp.insert(1ull << q);
                 for (int64_t k : s) sp.insert(T[k].x);
                 Dt = std::min(Dcap, std::max(sp.dim(), 2 * kRegBits + kXBits));
             }
-            sd_status st = build_pass(n, T, (int32_t)g, s, Dt, cc, &ps);
+            sd_status st = build_pass(n, T, (int32_t)g, s, Dt, cg, &ps);
             if (st != SD_OK) return st;
             P.passes.push_back(std::move(ps));
         }

@@ -184,10 +184,12 @@ struct Program {
 
 // shrink: give each pass the smallest tile (down to 2^10) that holds it, so
 // that small passes run several blocks per CU (complex64 runs faster so;
-// complex128 keeps D_max)
+// complex128 keeps D_max).  c: contiguous low address bits of every tile;
+// c_min < c lets a group's passes take down to c_min (at most two fewer)
+// where the cost model finds that cheaper (fewer passes).
 sd_status compile_program(int n, const std::vector<Term> &terms,
                           const std::vector<std::vector<int64_t>> &groups,
-                          int D_max, int c, Program *out, bool shrink);
+                          int D_max, int c, int c_min, Program *out, bool shrink);
 
 // bytes of the packed device records of a program (device.hip)
 int64_t pack_size(const Program &P);

@@ -261,6 +261,39 @@ def test_ensemble_of_uneven_instances(dtype):
     sd.sd_ensemble_destroy(ens)
 
 
+def test_ensemble_after_plan_rebind():
+    # a member plan rebound to a new workspace (the old one released) between
+    # two ensemble calls: the second call must use the new workspace, not the
+    # step captured with the old one
+    models = workloads.xxz_ensemble(count=3, seed=14, nmin=12, nmax=14, steps=10)
+    print("[gpu] ensemble rebind sizes", [m.n for m in models], flush=True)
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in models]
+    ens = sd.sd_ensemble_create([p.p for p in plans], sd.SD_C64)
+    ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+    sd.sd_ensemble_bind_workspace(ens, ws)
+    states = [torch.from_numpy(m.initial_state()).to(torch.complex64).cuda() for m in models]
+    singles = [s.clone() for s in states]
+    sd.sd_ensemble_evolve(ens, states, 0.05, 4, 2)
+    torch.cuda.synchronize()
+    old = plans[1].workspace
+    plans[1].bind()                  # new workspace tensor, same contents
+    # the old memory now holds the tables of another valid plan of the same
+    # shape (the same strings, other coefficients): a step captured with the
+    # old workspace would run that plan instead
+    m1 = models[1]
+    other = sd.Plan(m1.n, m1.paulis, np.asarray(m1.coeffs) * 1.5)
+    assert other.info.workspace_bytes == plans[1].info.workspace_bytes
+    sd.sd_bind_workspace(other.p, old)
+    sd.sd_ensemble_evolve(ens, states, 0.05, 6, 2)
+    for p, s in zip(plans, singles):
+        p.evolve(s, 0.05, 10, 2)
+    torch.cuda.synchronize()
+    for m, s, s1 in zip(models, states, singles):
+        assert torch.equal(s, s1), m.n
+    sd.sd_ensemble_destroy(ens)
+    other.close()
+
+
 @pytest.mark.parametrize("mode", [sd.SD_MODE_PAPER_LAYERS, sd.SD_MODE_TERMWISE])
 @pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
 @pytest.mark.parametrize("order", [2, 4])
