@@ -67,6 +67,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def applications_per_step(K, order):
+    """Group applications (C_g, Lambda_g, C_g^dagger) in one Trotter step:
+    the unit of the algorithmic bytes, one read and one write of the state
+    each.  Order 1: K; order 2 (Strang): 2K - 1; order 4: five Strang
+    steps."""
+    if K <= 1:
+        return {1: 1, 2: 1, 4: 5}[order] if K == 1 else 0
+    return {1: K, 2: 2 * K - 1, 4: 5 * (2 * K - 1)}[order]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def paper_sweep(args, torch, workloads, sd):
     """The paper's experiments on this GPU: one first-order Trotter step
     (dt = 0.01) for n = nmin..nmax of
@@ -129,13 +150,15 @@ def paper_sweep(args, torch, workloads, sd):
 def ensemble_experiment(args, torch, workloads, sd):
     """The ensemble workload on this GPU: 256 open XXZ chains, n_i ~ U{14..20}
     (seed 4), Neel states, second order at dt = 0.05, evolved together by
-    sd_ensemble_evolve (one multi-instance tile launch per pass level, one
-    step replayed as a HIP graph).  Timed: --steps steps after --warmup, for
-    complex64 and complex128; beside it the same instances evolved one after
-    another with sd_evolve.  Algorithmic bytes: every pass of every instance
-    reads and writes its state once, 2 * 2^n_i * B bytes.  Accuracy: mean and
-    worst 1 - F between the complex64 and complex128 ensembles after the same
-    steps."""
+    sd_ensemble_evolve (one multi-instance tile launch per pass level and
+    tile size, one step replayed as a HIP graph).  Timed: --steps steps after
+    --warmup, for complex64 and complex128; beside it the same instances
+    evolved one after another with sd_evolve.  Algorithmic bytes: every group
+    application of every instance reads and writes its state once,
+    2 * 2^n_i * B bytes (5 applications per second-order step of the three
+    XXZ groups); the bytes of all passes (sub-groups) are given beside them.
+    Accuracy: mean and worst 1 - F between the complex64 and complex128
+    ensembles after the same steps."""
     import numpy as np
     stream = torch.cuda.current_stream()
     models = workloads.xxz_ensemble()
@@ -178,7 +201,11 @@ def ensemble_experiment(args, torch, workloads, sd):
             run(args.warmup)
         sec = timed(run, args.steps)
         launches = sum(passes_per_step(p, dtype) for p in plans)
-        step_bytes = sum(passes_per_step(p, dtype) * 2 * (1 << m.n) * B for p, m in zip(plans, models))
+        # algorithmic bytes: one read and one write of an instance's state per
+        # group application (2K - 1 of them in a second-order step)
+        step_bytes = sum(applications_per_step(int(p.info.n_groups), order) * 2 * (1 << m.n) * B
+                         for p, m in zip(plans, models))
+        pass_bytes = sum(passes_per_step(p, dtype) * 2 * (1 << m.n) * B for p, m in zip(plans, models))
         gbps = step_bytes * args.steps / sec / 1e9
         # the same instances one after another (warm-up of the same length)
         seq = [torch.from_numpy(m.initial_state()).to(tdt).cuda() for m in models]
@@ -192,7 +219,9 @@ def ensemble_experiment(args, torch, workloads, sd):
         res[name] = {"steps_per_s": round(args.steps / sec, 3),
                      "ms_per_step": round(1e3 * sec / args.steps, 4),
                      "instance_passes_per_step": launches,
-                     "bytes_per_step": step_bytes,
+                     "algorithmic_bytes_per_step": step_bytes,
+                     "pass_bytes_per_step": pass_bytes,
+                     "hbm_gbps_per_pass_bytes": round(pass_bytes * args.steps / sec / 1e9, 1),
                      "hbm_gbps_algorithmic": round(gbps, 1),
                      "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
                      "one_by_one_steps_per_s": round(ks / sec_seq, 3),
@@ -218,6 +247,110 @@ def ensemble_experiment(args, torch, workloads, sd):
     print(json.dumps(out), flush=True)
 
 
+def config_experiment(args, torch, workloads, sd):
+    """Configurations 2 and 5 on this GPU, one JSON line each:
+      xxz26: periodic XXZ chain with random fields, n = 26, K = 3 groups,
+        second order, dt = 0.05 (Neel state);
+      jw32: Jordan-Wigner-shaped fermionic Hamiltonian, n = 32, 10^4 terms,
+        second order, dt = 0.02 (Hartree-Fock-like basis state; the state
+        takes 32 GiB in complex64, 64 GiB in complex128).
+    Timed: steps of the complex64 and complex128 paths (HIP events on the
+    launch stream).  Algorithmic bytes: one read and one write of the state
+    per group application, 2K - 1 applications per second-order step.
+    Accuracy: complex64 against complex128 after the same steps from the same
+    state (1000 steps for xxz26, one for jw32)."""
+    stream = torch.cuda.current_stream()
+    if args.experiment == "xxz26":
+        m = workloads.xxz_chain(26)
+        steps, warm, acc_steps = max(args.steps, 100), max(args.warmup, 2), 1000
+    else:
+        m = workloads.jw_fermionic(32)
+        steps, warm, acc_steps = 1, 0, 1
+    n, dt, order = m.n, m.dt, 2
+    t0 = time.time()
+    plan = sd.Plan(n, m.paulis, m.coeffs).bind("cuda")
+    plan_s = time.time() - t0
+    info = plan.info
+    K = int(info.n_groups)
+    apps = applications_per_step(K, order)
+    log(f"{args.experiment}: {info.n_terms} terms, {K} groups, passes c64 {info.passes_c64} "
+        f"c128 {info.passes_c128}, planned in {plan_s:.1f} s")
+
+    def state(tdt):
+        st = torch.zeros(1 << n, dtype=tdt, device="cuda")
+        st[int(m.init_index) if m.init == "basis" else workloads.neel_index(n)] = 1.0
+        return st
+
+    def timed(st, k):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.evolve(st, dt, k, order)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    res = {}
+    for name, tdt, B in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+        st = state(tdt)
+        if warm:
+            plan.evolve(st, dt, warm, order)
+        sec = timed(st, steps)
+        alg = apps * 2 * (1 << n) * B
+        passes = int(info.passes_c64 if B == 8 else info.passes_c128)
+        gbps = alg * steps / sec / 1e9
+        res[name] = {"steps_per_s": round(steps / sec, 4), "ms_per_step": round(1e3 * sec / steps, 3),
+                     "launches_per_step": _order2_launches(plan, sd.SD_C64 if B == 8 else sd.SD_C128),
+                     "passes_per_order1_step": passes,
+                     "algorithmic_bytes_per_step": alg, "hbm_gbps_algorithmic": round(gbps, 1),
+                     "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+        log(f"{args.experiment} {name}: {res[name]}")
+        del st
+    # accuracy: the same steps from the same state in both precisions
+    a = state(torch.complex64)
+    b = state(torch.complex128)
+    done = 0
+    while done < acc_steps:
+        k = min(100, acc_steps - done)
+        plan.evolve(a, dt, k, order)
+        plan.evolve(b, dt, k, order)
+        torch.cuda.synchronize()
+        done += k
+    l2sq, mx = 0.0, 0.0
+    for i in range(0, a.numel(), 1 << 26):
+        d = a[i:i + (1 << 26)].to(torch.complex128) - b[i:i + (1 << 26)]
+        l2sq += float(torch.sum(d.real * d.real + d.imag * d.imag))
+        mx = max(mx, float(d.abs().max()))
+    na, nb = sd.sd_norm2(a, n), sd.sd_norm2(b, n)
+    ov = 0j
+    for i in range(0, a.numel(), 1 << 28):
+        aa = a[i:i + (1 << 28)].to(torch.complex128)
+        ov += complex(torch.vdot(b[i:i + (1 << 28)], aa))
+    fid = abs(ov) ** 2 / (na * nb)
+    out = {"experiment": args.experiment,
+           "metric": "Trotter steps/s (grouped), c64 amplitudes + FP64 phase vs c128",
+           "unit": "steps/s",
+           "config": {"workload": "xxz_periodic_n26" if n == 26 else "jw_fermionic_n32",
+                      "n_qubits": n, "terms": int(info.n_terms), "groups": K, "order": order,
+                      "dt": dt, "initial_state": m.init},
+           "plan_seconds": round(plan_s, 2), "timed_steps": steps, "warmup": warm,
+           "group_applications_per_step": apps, **res,
+           "c64_over_c128": round(res["c64"]["steps_per_s"] / res["c128"]["steps_per_s"], 3),
+           "accuracy_c64_vs_c128": {"steps": acc_steps, "l2": l2sq ** 0.5, "max_abs": mx,
+                                    "1_minus_fidelity": 1.0 - fid, "norm_drift_c64": na - 1.0,
+                                    "norm_drift_c128": nb - 1.0}}
+    print(json.dumps(out), flush=True)
+
+
+def _order2_launches(plan, dtype):
+    per_group = collections.Counter(ps["group"] for ps in plan.passes(dtype))
+    K = int(plan.info.n_groups)
+    if K <= 1:
+        return sum(per_group.values())
+    return 2 * sum(per_group[g] for g in range(K - 1)) + per_group[K - 1]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,11 +359,13 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
-    ap.add_argument("--cpu-sample-terms", type=int, default=320)
-    ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep", "ensemble"], default=None,
+    ap.add_argument("--cpu-sample-terms", type=int, default=128)
+    ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep", "ensemble", "xxz26", "jw32"],
+                    default=None,
                     help="instead of the benchmark line: the paper's fully connected TFIM "
                          "or SYK Majorana sweep, grouped vs term by term (one JSON line per n), "
-                         "or the 256-instance XXZ ensemble (one JSON line)")
+                         "the 256-instance XXZ ensemble, the XXZ chain at n = 26 or the "
+                         "Jordan-Wigner workload at n = 32 (one JSON line each)")
     ap.add_argument("--nstep", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true",
                     help="plan with the default tile sizes (2^13) instead of autotuning them; "
@@ -258,6 +393,9 @@ def main():
     if args.experiment == "ensemble":
         ensemble_experiment(args, torch, workloads, sd)
         return
+    if args.experiment in ("xxz26", "jw32"):
+        config_experiment(args, torch, workloads, sd)
+        return
     if args.experiment:
         paper_sweep(args, torch, workloads, sd)
         return
@@ -279,7 +417,10 @@ def main():
         scratch = d128_0.to(tdt)
         best, secs = sd.sd_autotune_tiles(h, dt_, scratch, m.dt, 1, 1, cands)
         del scratch
-        size = best.tile_log2_c64 if dt_ == sd.SD_C64 else best.tile_log2_c128
+        # the largest tile within 1% of the fastest: as fast within the
+        # timing noise, and the fewest passes (each pass rounds every
+        # complex64 amplitude once)
+        size = max(c for c, t in zip(cands, secs) if t <= 1.01 * min(secs))
         if dt_ == sd.SD_C64:
             opts.tile_log2_c64 = size
         else:
@@ -354,11 +495,20 @@ def main():
         log(f"calibration copy: {dim * 8} bytes read, {dim * 8} bytes written")
         del src, dst
 
+    # Roofline by group applications (the method's unit): every application
+    # of a group reads and writes the state once, 2 * 2^n * B bytes.  A
+    # launch is one tile pass; a group split into sub-groups takes several,
+    # so one launch does applications / passes of a unit.
+    K = int(info.n_groups)
+    apps = applications_per_step(K, 1)
+    unit64 = 2 * dim * 8
+    alg_step64 = apps * unit64
     launches = args.steps * info.passes_c64
     avg_launch_s = t64 / launches
-    bytes_per_launch = 2 * dim * 8
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = counter_traffic()
+    achieved = alg_step64 * args.steps / t64 / 1e9        # = (apps / passes) * unit / avg launch
+    pass_gbps = unit64 / avg_launch_s / 1e9               # what one pass moves per launch time
+    traffic = counter_traffic()                           # counter bytes per launch (or None)
+    alg_step128 = apps * 2 * dim * 16
     result = {
         "metric": "Trotter steps/s (grouped, c64 amplitudes + FP64 phase), n=28 random k-local",
         "value": round(sps64, 4),
@@ -373,17 +523,22 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "random_klocal_n28", "n_qubits": n, "terms": int(info.n_terms),
-                   "groups": int(info.n_groups), "order": 1, "dt": m.dt,
+                   "groups": K, "order": 1, "dt": m.dt,
                    "storage": "complex64", "seed": 3, "init_seed": m.init_seed,
-                   "tile_log2_c64": int(opts.tile_log2_c64), "tile_log2_c128": int(opts.tile_log2_c128)},
+                   "tile_log2_c64": int(opts.tile_log2_c64), "tile_log2_c128": int(opts.tile_log2_c128),
+                   "coalesce_log2_c64": int(opts.coalesce_log2_c64),
+                   "coalesce_min_log2_c64": int(opts.coalesce_min_log2_c64)},
         "autotune": tune,
         "c128_steps_per_s": round(sps128, 4),
         "c64_over_c128": round(sps64 / sps128, 3),
+        "group_applications_per_step": apps,
         "passes_per_step_c64": int(info.passes_c64),
         "passes_per_step_c128": int(info.passes_c128),
         "paper_model_passes_per_step": int(info.paper_model_passes),
+        "algorithmic_bytes_per_step_c64": alg_step64,
         "hbm_gbps_algorithmic_c64": round(achieved, 1),
-        "hbm_gbps_algorithmic_c128": round(2 * dim * 16 * k128 * info.passes_c128 / t128 / 1e9, 1),
+        "hbm_gbps_algorithmic_c128": round(alg_step128 * k128 / t128 / 1e9, 1),
+        "frac_of_hbm_peak_c128": round(alg_step128 * k128 / t128 / 1e9 / HBM_PEAK_GBPS, 4),
         "accuracy_c64_vs_c128": {"steps": steps_acc, "fidelity": fid, "l2": l2, "max_abs": maxerr,
                                  "norm_drift_c64": n64 - 1.0, "norm_drift_c128": n128 - 1.0,
                                  "energy_drift_c64": e64 - e0, "energy_drift_c128": e128 - e0},
@@ -392,7 +547,13 @@ def main():
                      "traffic": traffic,
                      "kernel": ROOFLINE_KERNEL,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "bytes_per_launch": bytes_per_launch},
+                     "units_per_launch": round(apps / info.passes_c64, 4),
+                     "bytes_per_unit": unit64,
+                     "pass_bytes_per_launch": unit64,
+                     "pass_gbps_per_launch": round(pass_gbps, 1),
+                     "traffic_per_step": None if traffic is None else traffic * int(info.passes_c64),
+                     "traffic_over_algorithmic": None if traffic is None
+                     else round(traffic * int(info.passes_c64) / alg_step64, 3)},
     }
 
     if not args.no_reference_modes:
@@ -420,27 +581,33 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        log("cpu baseline (oracle sample)")
+        log("cpu baseline (oracle sample, 3 runs)")
         t = oracle.build_terms(n, m.paulis, m.coeffs)
         k = min(args.cpu_sample_terms, len(t.c))
         import ctypes
-        psi = psi_host.copy()
         xs = np.ascontiguousarray(t.x[:k], dtype=np.uint64)
         zs = np.ascontiguousarray(t.z[:k], dtype=np.uint64)
         th = np.ascontiguousarray(t.c[:k] * m.dt, dtype=np.float64)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         dp = ctypes.POINTER(ctypes.c_double)
-        ts = time.time()
-        oracle.lib().or_apply_rotations(n, psi.view(np.float64).ctypes.data_as(dp), k,
-                                        xs.ctypes.data_as(u64p), zs.ctypes.data_as(u64p),
-                                        th.ctypes.data_as(dp))
-        dt_s = time.time() - ts
-        per_rot = dt_s / k
+        runs = []
+        for _ in range(3):
+            psi = psi_host.copy()
+            ts = time.time()
+            oracle.lib().or_apply_rotations(n, psi.view(np.float64).ctypes.data_as(dp), k,
+                                            xs.ctypes.data_as(u64p), zs.ctypes.data_as(u64p),
+                                            th.ctypes.data_as(dp))
+            runs.append(time.time() - ts)
+            del psi
+        med = sorted(runs)[1]
+        per_rot = med / k
         result["cpu_baseline"] = {
             "value": round(1.0 / (per_rot * len(t.c)), 6), "unit": "steps/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{k} of {len(t.c)} term rotations of one Trotter step at n={n} "
-                      f"(FP64, {dt_s:.1f} s); steps/s = 1/(time per rotation x {len(t.c)})"}
+            "cpu": cpu_model(),
+            "sample": f"{k} of {len(t.c)} term rotations of one Trotter step at n={n} (FP64), "
+                      f"median of 3 runs ({', '.join(f'{r:.1f}' for r in runs)} s); "
+                      f"steps/s = 1/(time per rotation x {len(t.c)})"}
     print(json.dumps(result), flush=True)
 
 

@@ -132,6 +132,11 @@ typedef struct {
        coalesce_log2_c64 keeps every pass at that width; negative values
        are SD_ERR_RANGE. */
     int32_t coalesce_min_log2_c64;
+    /* complex64: 1 (default) gives each pass the smallest tile (at least
+       2^10) that holds its sub-group, so that small passes run several
+       blocks per CU; 0 keeps every pass at min(tile_log2_c64, n_qubits)
+       (one tile size for the whole plan, as complex128 always has). */
+    int32_t tile_shrink_c64;
 } sd_plan_options;
 
 enum { SD_MODE_TILES = 0, SD_MODE_PAPER_LAYERS = 1, SD_MODE_TERMWISE = 2 };
@@ -372,7 +377,8 @@ sd_status sd_inner_noalloc(const void *a, const void *b, sd_dtype dtype, int32_t
 
 /* Ensemble of independent instances (uneven sizes allowed), evolved together.
    plans: `count` plans, each with a bound workspace; states: host array of
-   `count` device pointers.  One launch per pass level per step.
+   `count` device pointers.  One launch per pass level (and tile size) per
+   step; one step is captured once as a HIP graph and replayed.
    sd_ensemble_workspace_bytes: the device bytes for the per-level segment
    tables, enough for every order (1, 2, 4); the caller allocates them
    (256-byte aligned) and binds them with sd_ensemble_bind_workspace before

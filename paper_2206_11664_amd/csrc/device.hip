@@ -676,23 +676,39 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
     const char *sbase = (const char *)state;
     // Tiles that differ only in free bits below the 128-byte line share every
     // line they touch (a pass with fewer than log2(128 / sizeof(T)) contiguous
-    // low bits).  The block then takes them one after the other: iteration k
-    // of block b (tile t0 + k * stride of the loop) runs tile
-    // ((k >> s) * stride + b) * 2^s + (k mod 2^s), a bijection of the tile
-    // range when stride * 2^s divides it, so that a line fetched for one tile
-    // is still in the cache for its partners, and their partial-line stores
-    // meet in the cache.  Strided launches only (a contiguous range already
-    // runs partners in a row).
+    // low bits; 2^s partners).  Strided launches run partners at the same
+    // time on one XCD: blocks are dealt to the 8 XCDs in turn (block b to XCD
+    // b mod 8), and iteration k of block b (tile t0 + k * stride of the loop)
+    // runs tile ((k * stride / 2^s + q * 8 + x) << s) | p with x = b mod 8,
+    // j = b / 8, p = j mod 2^s, q = j / 2^s: the partners of a tile are the
+    // same iteration of blocks b, b + 8, ..., so one fetch of a line from
+    // memory serves all of them from that XCD's L2, and their partial-line
+    // stores meet there.  Each iteration covers tiles k * stride ..
+    // (k + 1) * stride - 1, a bijection when stride is a multiple of 8 * 2^s
+    // dividing the tile count; otherwise a block runs the partners one after
+    // the other (iteration k runs ((k >> s) * stride + b) * 2^s + (k mod 2^s),
+    // a bijection when stride * 2^s divides the tile count).  The mapping
+    // only changes the order of independent tiles.  Contiguous ranges (the
+    // ensemble kernels) run partners in a row already.
     int sh = 0;
+    bool xcd = false;
     if (stride > 1) {
         const int line_bits = sizeof(T) == 8 ? 4 : 3;
         while (sh < pd.n_free && pd.free_pos[sh] < line_bits) ++sh;
-        if (t1 % (stride << sh) != 0 || t0 >= stride) sh = 0;
+        if (t0 >= stride || t1 % stride != 0) sh = 0;
+        xcd = sh && stride % (8 << sh) == 0;
+        if (sh && !xcd && t1 % (stride << sh) != 0) sh = 0;
     }
     auto tile_off = [&](int64_t ti) {
         if (sh) {
             const int64_t k = (ti - t0) / stride;
-            ti = (((k >> sh) * stride + t0) << sh) | (k & ((1 << sh) - 1));
+            if (xcd) {
+                const int64_t x = t0 & 7, j = t0 >> 3;
+                const int64_t p = j & ((1 << sh) - 1), q = j >> sh;
+                ti = ((k * (stride >> sh) + q * 8 + x) << sh) | p;
+            } else {
+                ti = (((k >> sh) * stride + t0) << sh) | (k & ((1 << sh) - 1));
+            }
         }
         uint64_t xT = 0;
         for (int i = 0; i < pd.n_free; ++i)

@@ -18,6 +18,7 @@ extern "C" void sd_plan_options_default(sd_plan_options *o) {
     o->coalesce_log2_c128 = 3;
     o->mode = SD_MODE_TILES;
     o->coalesce_min_log2_c64 = 2;
+    o->tile_shrink_c64 = 1;
 }
 
 namespace {
@@ -105,7 +106,7 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
     sd_status st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c64,
                                    opt.coalesce_log2_c64,
                                    std::min(opt.coalesce_min_log2_c64, opt.coalesce_log2_c64),
-                                   &p->prog[SD_C64], true);
+                                   &p->prog[SD_C64], opt.tile_shrink_c64 != 0);
     if (st == SD_OK)
         st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c128,
                              opt.coalesce_log2_c128, opt.coalesce_log2_c128, &p->prog[SD_C128], false);

@@ -236,13 +236,19 @@ def test_full_size_n28_widest_group_vs_oracle():
         assert err <= (1e-10 if dtype == sd.SD_C128 else 1e-6)
 
 
+@pytest.mark.parametrize("shrink", [1, 0])
 @pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
-def test_ensemble_of_uneven_instances(dtype):
-    # uneven sizes; n = 8 runs below the multi-instance kernel's tile minimum
+def test_ensemble_of_uneven_instances(dtype, shrink):
+    # uneven sizes; n = 8 runs below the multi-instance kernel's tile minimum.
+    # Plans with one tile size per plan (complex128 always, complex64 without
+    # tile shrinking) and plans with several: the ensemble must equal each
+    # instance's own sd_evolve bit for bit.
     models = workloads.xxz_ensemble(count=5, seed=4, nmin=8, nmax=15, steps=20)
     models[0] = workloads.xxz_ensemble(count=1, seed=9, nmin=8, nmax=8, steps=20)[0]
-    print("[gpu] ensemble sizes", [m.n for m in models], flush=True)
-    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in models]
+    print(f"[gpu] ensemble sizes {[m.n for m in models]} dtype={dtype} shrink={shrink}", flush=True)
+    o = sd.sd_plan_options_default()
+    o.tile_shrink_c64 = shrink
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs, o).bind() for m in models]
     ens = sd.sd_ensemble_create([p.p for p in plans], dtype)
     ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
     sd.sd_ensemble_bind_workspace(ens, ws)
@@ -261,13 +267,16 @@ def test_ensemble_of_uneven_instances(dtype):
     sd.sd_ensemble_destroy(ens)
 
 
-def test_ensemble_after_plan_rebind():
+@pytest.mark.parametrize("shrink", [1, 0])
+def test_ensemble_after_plan_rebind(shrink):
     # a member plan rebound to a new workspace (the old one released) between
     # two ensemble calls: the second call must use the new workspace, not the
-    # step captured with the old one
+    # step captured with the old one (plans with one or several tile sizes)
     models = workloads.xxz_ensemble(count=3, seed=14, nmin=12, nmax=14, steps=10)
-    print("[gpu] ensemble rebind sizes", [m.n for m in models], flush=True)
-    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in models]
+    print(f"[gpu] ensemble rebind sizes {[m.n for m in models]} shrink={shrink}", flush=True)
+    o = sd.sd_plan_options_default()
+    o.tile_shrink_c64 = shrink
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs, o).bind() for m in models]
     ens = sd.sd_ensemble_create([p.p for p in plans], sd.SD_C64)
     ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
     sd.sd_ensemble_bind_workspace(ens, ws)
@@ -281,7 +290,7 @@ def test_ensemble_after_plan_rebind():
     # shape (the same strings, other coefficients): a step captured with the
     # old workspace would run that plan instead
     m1 = models[1]
-    other = sd.Plan(m1.n, m1.paulis, np.asarray(m1.coeffs) * 1.5)
+    other = sd.Plan(m1.n, m1.paulis, np.asarray(m1.coeffs) * 1.5, o)
     assert other.info.workspace_bytes == plans[1].info.workspace_bytes
     sd.sd_bind_workspace(other.p, old)
     sd.sd_ensemble_evolve(ens, states, 0.05, 6, 2)
@@ -292,6 +301,17 @@ def test_ensemble_after_plan_rebind():
         assert torch.equal(s, s1), m.n
     sd.sd_ensemble_destroy(ens)
     other.close()
+
+
+@pytest.mark.skip(reason="the persistent one-launch ensemble step is switched off: a version with "
+                         "per-instance counters of finished tiles and waits on them ran without finishing "
+                         "on MI355X (killed after 180 s without output, twice, in the 5-instance complex128 "
+                         "ensemble below); the cause was not shown, so the step is not built")
+def test_ensemble_persistent_step():
+    # kept as the record of the case: 5 XXZ instances n = [8, 15, 15, 12, 15],
+    # complex128, 20 second-order steps, the persistent step against each
+    # instance's own sd_evolve
+    raise AssertionError("not built")
 
 
 @pytest.mark.parametrize("mode", [sd.SD_MODE_PAPER_LAYERS, sd.SD_MODE_TERMWISE])

@@ -17,6 +17,7 @@ from .hamiltonians import (  # noqa: F401
     syk_majorana,
     xxz_ensemble,
     neel_state,
+    neel_index,
     basis_state,
     random_state,
     config,
