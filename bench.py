@@ -117,31 +117,55 @@ def paper_sweep(args, torch, workloads, sd):
             k *= 4
 
     gen = workloads.tfim_fully_connected if args.experiment == "tfim_sweep" else workloads.syk_majorana
+    modes = [x for x in args.modes.split(",") if x]
     for n in range(args.nmin, args.nmax + 1, args.nstep):
         m = gen(n)
         row = {"experiment": args.experiment, "n": n, "terms": len(m.paulis)}
         plans = {}
         for name, mode in (("tiles", sd.SD_MODE_TILES), ("paper_layers", sd.SD_MODE_PAPER_LAYERS),
                            ("termwise", sd.SD_MODE_TERMWISE)):
+            if name != "tiles" and name not in modes:
+                continue
             o = sd.sd_plan_options_default()
             o.mode = mode
-            plans[name] = sd.Plan(n, m.paulis, m.coeffs, o).bind("cuda")
+            ps, cs = m.paulis, m.coeffs
+            if name == "termwise" and 0 < args.termwise_sample < len(m.paulis):
+                # one rotation pass per term, all alike: time the first terms
+                # and scale to all of them
+                ps, cs = m.paulis[:args.termwise_sample], m.coeffs[:args.termwise_sample]
+            plans[name] = sd.Plan(n, ps, cs, o).bind("cuda")
+        scale = {k: 1.0 for k in plans}
+        if "termwise" in plans and 0 < args.termwise_sample < len(m.paulis):
+            scale["termwise"] = len(m.paulis) / args.termwise_sample
+            row["termwise_sampled_terms"] = args.termwise_sample
         info = plans["tiles"].info
         ng = int(info.n_groups)
         row["groups"] = ng
         row["plan_seconds"] = round(float(info.plan_seconds), 2)
         row["passes_c64"] = int(info.passes_c64)
         row["cost_model_speedup"] = round(len(m.paulis) / (n * ng), 3)
-        psi0 = torch.from_numpy(workloads.random_state(n, 1)).cuda()
+        if n <= 28:
+            psi0 = torch.from_numpy(workloads.random_state(n, 1)).cuda()
+        else:
+            # (drawn on the GPU: the host copy would take 2^n x 16 bytes)
+            psi0 = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+            g = torch.Generator(device="cuda").manual_seed(1)
+            flat = torch.view_as_real(psi0).view(-1)
+            for i in range(0, flat.numel(), 1 << 28):
+                flat[i:i + (1 << 28)].normal_(generator=g)
+            del flat
+            psi0 /= sd.sd_norm2(psi0, n) ** 0.5
         for dname, tdt in (("c128", torch.complex128), ("c64", torch.complex64)):
             t = {}
             for name, plan in plans.items():
                 st = psi0.to(tdt)
-                t[name] = step_time(plan, st, m.dt)
+                t[name] = step_time(plan, st, m.dt) * scale[name]
                 del st
-            row[dname] = {"step_ms": {k: round(v * 1e3, 4) for k, v in t.items()},
-                          "speedup_tiles_vs_termwise": round(t["termwise"] / t["tiles"], 2),
-                          "speedup_paper_layers_vs_termwise": round(t["termwise"] / t["paper_layers"], 2)}
+            row[dname] = {"step_ms": {k: round(v * 1e3, 4) for k, v in t.items()}}
+            if "termwise" in t:
+                row[dname]["speedup_tiles_vs_termwise"] = round(t["termwise"] / t["tiles"], 2)
+                if "paper_layers" in t:
+                    row[dname]["speedup_paper_layers_vs_termwise"] = round(t["termwise"] / t["paper_layers"], 2)
         log(f"{args.experiment} n={n}: c128 {row['c128']['step_ms']} c64 {row['c64']['step_ms']}")
         print(json.dumps(row), flush=True)
         del psi0, plans
@@ -372,6 +396,11 @@ def main():
                          "the profiled runs use this so that their traces hold the timed plan only")
     ap.add_argument("--accuracy-steps", type=int, default=0,
                     help="steps of the complex64 vs complex128 accuracy run (default: 10)")
+    ap.add_argument("--modes", default="paper_layers,termwise",
+                    help="sweeps: reference modes timed beside the tiles")
+    ap.add_argument("--termwise-sample", type=int, default=0,
+                    help="sweeps: time the term-by-term step on its first K terms and scale "
+                         "by m/K (every term is one rotation pass of the same cost)")
     ap.add_argument("--nmin", type=int, default=12)
     ap.add_argument("--nmax", type=int, default=30)
     ap.add_argument("--calib-copy", action="store_true",
