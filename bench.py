@@ -67,14 +67,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def step_groups(K, order):
+    """Group applications of one Trotter step in a run of many steps, as
+    (group, fraction of dt): order 1 the groups in order; order 2 (Strang)
+    G_0..G_{K-2} at dt/2, G_{K-1} at dt, back down to G_0 at dt/2; order 4
+    five Strang steps (Suzuki).  Applications of one group that follow each
+    other are joined into one, inside a step and across the step boundary
+    (the steady-state step of a call of many steps)."""
+    if K <= 0:
+        return []
+    if order == 1 or K == 1:
+        seq = [(g, 1.0) for g in range(K)]
+    else:
+        s2 = [(g, 0.5) for g in range(K - 1)] + [(K - 1, 1.0)] + [(g, 0.5) for g in range(K - 2, -1, -1)]
+        if order == 2:
+            seq = s2
+        else:
+            p = 1.0 / (4.0 - 4.0 ** (1.0 / 3.0))
+            seq = [(g, f * w) for w in (p, p, 1.0 - 4.0 * p, p, p) for g, f in s2]
+    m = []
+    for g, f in seq:
+        if m and m[-1][0] == g:
+            m[-1] = (g, m[-1][1] + f)
+        else:
+            m.append((g, f))
+    if len(m) >= 2 and m[0][0] == m[-1][0]:
+        m = m[1:-1] + [(m[-1][0], m[-1][1] + m[0][1])]
+    return m
+
+
 def applications_per_step(K, order):
-    """Group applications (C_g, Lambda_g, C_g^dagger) in one Trotter step:
-    the unit of the algorithmic bytes, one read and one write of the state
-    each.  Order 1: K; order 2 (Strang): 2K - 1; order 4: five Strang
-    steps."""
-    if K <= 1:
-        return {1: 1, 2: 1, 4: 5}[order] if K == 1 else 0
-    return {1: K, 2: 2 * K - 1, 4: 5 * (2 * K - 1)}[order]
+    """Group applications (C_g, Lambda_g, C_g^dagger) in one steady-state
+    Trotter step: the unit of the algorithmic bytes, one read and one write
+    of the state each.  Order 1: K; order 2 (Strang, the G_0 halves of
+    consecutive steps joined): 2K - 2 for K > 1; order 4: 5 (2K - 2)."""
+    return len(step_groups(K, order))
+
+
+def passes_per_step(plan, dtype, order):
+    """Tile passes (launches) of one steady-state step of a plan."""
+    per_group = collections.Counter(ps["group"] for ps in plan.passes(dtype))
+    return sum(per_group[g] for g, _ in step_groups(int(plan.info.n_groups), order))
 
 
 def cpu_model():
@@ -179,8 +212,9 @@ def ensemble_experiment(args, torch, workloads, sd):
     --warmup, for complex64 and complex128; beside it the same instances
     evolved one after another with sd_evolve.  Algorithmic bytes: every group
     application of every instance reads and writes its state once,
-    2 * 2^n_i * B bytes (5 applications per second-order step of the three
-    XXZ groups); the bytes of all passes (sub-groups) are given beside them.
+    2 * 2^n_i * B bytes (4 applications per second-order step of the three
+    XXZ groups, the G_0 halves of consecutive steps joined); the bytes of all
+    passes (sub-groups) are given beside them.
     Accuracy: mean and worst 1 - F between the complex64 and complex128
     ensembles after the same steps."""
     import numpy as np
@@ -192,14 +226,6 @@ def ensemble_experiment(args, torch, workloads, sd):
     plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind("cuda") for m in models]
     plan_s = time.time() - t0
     amps = sum(1 << m.n for m in models)
-
-    def passes_per_step(plan, dtype):
-        # the order-2 schedule: groups 0..K-2 twice (half steps), K-1 once
-        per_group = collections.Counter(ps["group"] for ps in plan.passes(dtype))
-        K = int(plan.info.n_groups)
-        if K <= 1:
-            return sum(per_group.values())
-        return 2 * sum(per_group[g] for g in range(K - 1)) + per_group[K - 1]
 
     def timed(fn, steps):
         torch.cuda.synchronize()
@@ -224,12 +250,13 @@ def ensemble_experiment(args, torch, workloads, sd):
         if args.warmup:
             run(args.warmup)
         sec = timed(run, args.steps)
-        launches = sum(passes_per_step(p, dtype) for p in plans)
+        launches = sum(passes_per_step(p, dtype, order) for p in plans)
         # algorithmic bytes: one read and one write of an instance's state per
-        # group application (2K - 1 of them in a second-order step)
+        # group application (2K - 2 of them in a second-order step whose G_0
+        # halves are joined with those of the neighbouring steps)
         step_bytes = sum(applications_per_step(int(p.info.n_groups), order) * 2 * (1 << m.n) * B
                          for p, m in zip(plans, models))
-        pass_bytes = sum(passes_per_step(p, dtype) * 2 * (1 << m.n) * B for p, m in zip(plans, models))
+        pass_bytes = sum(passes_per_step(p, dtype, order) * 2 * (1 << m.n) * B for p, m in zip(plans, models))
         gbps = step_bytes * args.steps / sec / 1e9
         # the same instances one after another (warm-up of the same length)
         seq = [torch.from_numpy(m.initial_state()).to(tdt).cuda() for m in models]
@@ -280,7 +307,8 @@ def config_experiment(args, torch, workloads, sd):
         takes 32 GiB in complex64, 64 GiB in complex128).
     Timed: steps of the complex64 and complex128 paths (HIP events on the
     launch stream).  Algorithmic bytes: one read and one write of the state
-    per group application, 2K - 1 applications per second-order step.
+    per group application, 2K - 2 applications per second-order step (the G_0
+    halves of consecutive steps joined).
     Accuracy: complex64 against complex128 after the same steps from the same
     state (1000 steps for xxz26, one for jw32)."""
     stream = torch.cuda.current_stream()
@@ -325,7 +353,7 @@ def config_experiment(args, torch, workloads, sd):
         passes = int(info.passes_c64 if B == 8 else info.passes_c128)
         gbps = alg * steps / sec / 1e9
         res[name] = {"steps_per_s": round(steps / sec, 4), "ms_per_step": round(1e3 * sec / steps, 3),
-                     "launches_per_step": _order2_launches(plan, sd.SD_C64 if B == 8 else sd.SD_C128),
+                     "launches_per_step": passes_per_step(plan, sd.SD_C64 if B == 8 else sd.SD_C128, order),
                      "passes_per_order1_step": passes,
                      "algorithmic_bytes_per_step": alg, "hbm_gbps_algorithmic": round(gbps, 1),
                      "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
@@ -365,14 +393,6 @@ def config_experiment(args, torch, workloads, sd):
                                     "1_minus_fidelity": 1.0 - fid, "norm_drift_c64": na - 1.0,
                                     "norm_drift_c128": nb - 1.0}}
     print(json.dumps(out), flush=True)
-
-
-def _order2_launches(plan, dtype):
-    per_group = collections.Counter(ps["group"] for ps in plan.passes(dtype))
-    K = int(plan.info.n_groups)
-    if K <= 1:
-        return sum(per_group.values())
-    return 2 * sum(per_group[g] for g in range(K - 1)) + per_group[K - 1]
 
 
 def main():

@@ -1337,6 +1337,44 @@ static std::vector<std::pair<int, double>> step_schedule(int K, int order) {
     return seq;
 }
 
+// The group applications of `steps` steps, merged where one group follows
+// itself: G_g(a) G_g(b) = G_g(a + b) exactly (a group is one exponential),
+// and each merge saves a pass over the state per sub-group (and, complex64,
+// one rounding of every amplitude).  Inside a step that joins the halves at
+// the boundaries of the second-order steps of order 4; across steps it joins
+// the last application of a step with the first of the next one when they
+// are the same group (order 2: G_0(dt/2) G_0(dt/2) = G_0(dt)).  The calls of
+// `steps` steps then run
+//   prologue, core x (steps - 1), epilogue
+// with core the step from its second application on, ending in the joined
+// one.  Without a join across steps the prologue is empty and core and
+// epilogue are the (inside-merged) step.  A result is that of `steps` whole
+// steps; only the grouping of the applications differs.
+struct CallSchedule {
+    std::vector<std::pair<int, double>> pro, core, epi;
+};
+
+static CallSchedule call_schedule(int K, int order) {
+    std::vector<std::pair<int, double>> m;
+    for (auto &gf : step_schedule(K, order)) {
+        if (!m.empty() && m.back().first == gf.first)
+            m.back().second += gf.second;
+        else
+            m.push_back(gf);
+    }
+    CallSchedule cs;
+    if (m.size() >= 2 && m.front().first == m.back().first) {
+        cs.pro.push_back(m.front());
+        cs.core.assign(m.begin() + 1, m.end() - 1);
+        cs.core.push_back({m.back().first, m.back().second + m.front().second});
+        cs.epi.assign(m.begin() + 1, m.end());
+    } else {
+        cs.core = m;
+        cs.epi = m;
+    }
+    return cs;
+}
+
 }  // namespace sd
 
 using namespace sd;
@@ -1389,25 +1427,27 @@ extern "C" sd_status sd_evolve(const sd_plan_t *p, void *state, sd_dtype dtype, 
     const Program &P = p->prog[dtype];
     const int K = (int)p->groups.size();
     if (K == 0 || steps == 0) return SD_OK;
-    auto seq = step_schedule(K, order);
-    if (p->mode != SD_MODE_TILES) {
-        for (int64_t st = 0; st < steps; ++st)
-            for (auto &gf : seq) {
-                sd_status r = run_group_reference(p, state, dtype, gf.first, dt * gf.second, s);
-                if (r != SD_OK) return r;
-            }
-        return SD_OK;
-    }
-    for (int64_t st = 0; st < steps; ++st)
+    const CallSchedule cs = call_schedule(K, order);
+    auto run = [&](const std::vector<std::pair<int, double>> &seq) -> sd_status {
         for (auto &gf : seq) {
             const double tau = dt * gf.second;
+            if (p->mode != SD_MODE_TILES) {
+                sd_status r = run_group_reference(p, state, dtype, gf.first, tau, s);
+                if (r != SD_OK) return r;
+                continue;
+            }
             for (int i = P.group_first[gf.first]; i < P.group_first[gf.first + 1]; ++i) {
                 sd_status r = dtype == SD_C64 ? launch_pass<float2, 0>(p, dtype, i, state, tau, s)
                                               : launch_pass<double2, 0>(p, dtype, i, state, tau, s);
                 if (r != SD_OK) return r;
             }
         }
-    return SD_OK;
+        return SD_OK;
+    };
+    sd_status r = run(cs.pro);
+    for (int64_t st = 1; st < steps && r == SD_OK; ++st) r = run(cs.core);
+    if (r == SD_OK) r = run(cs.epi);
+    return r;
 }
 
 extern "C" sd_status sd_expectation(const sd_plan_t *p, const void *state, sd_dtype dtype,
@@ -1724,32 +1764,46 @@ extern "C" sd_status sd_autotune_tiles(const sd_hamiltonian *h, const sd_plan_op
 // ensemble
 // ---------------------------------------------------------------------------
 // Instances are independent; within an instance the passes of a step are
-// sequential.  Level l of a step holds pass l of the step's pass sequence of
-// every instance that has one; a level is one k_tile_multi launch over all
-// its instances' tiles (grouped by tile size), so a step costs as many
-// launches as the longest instance sequence, whatever the number of
-// instances.  One step's launches are captured once as a HIP graph on an
-// internal stream and replayed.
+// sequential.  Level l of a part of a call (see call_schedule: prologue,
+// core step, epilogue) holds pass l of that part's pass sequence of every
+// instance that has one; a level is one k_tile_multi launch over all its
+// instances' tiles (grouped by tile size), so a part costs as many launches
+// as the longest instance sequence, whatever the number of instances.  Each
+// part's launches are captured once as a HIP graph on an internal stream
+// and replayed: a call of S steps replays the prologue once, the core S - 1
+// times and the epilogue once, exactly as sd_evolve runs each instance.
+constexpr int kParts = 3;  // prologue, core, epilogue
+
 struct sd_ensemble {
     std::vector<const sd_plan_t *> plans;
     sd_dtype dtype = SD_C64;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     int64_t ws_needed = 0;
+    int64_t part_bytes = 0;  // segment table bytes of one part
     int max_levels = 0;
     // graph cache
     hipStream_t cstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[kParts] = {};
+    hipGraphExec_t exec[kParts] = {};
+    bool cached = false;
     double g_dt = 0;
     int g_order = 0;
     std::vector<void *> g_states;
-    std::vector<const void *> g_plan_ws;  // each plan's workspace when the graph was built
-    std::vector<int> g_small;   // instances run through sd_evolve each step
+    std::vector<const void *> g_plan_ws;  // each plan's workspace when the graphs were built
+    std::vector<int> g_small;   // instances run through sd_evolve's pass launches instead
+    void drop_graphs() {
+        for (int q = 0; q < kParts; ++q) {
+            if (exec[q]) (void)hipGraphExecDestroy(exec[q]);
+            if (graph[q]) (void)hipGraphDestroy(graph[q]);
+            exec[q] = nullptr;
+            graph[q] = nullptr;
+        }
+        cached = false;
+    }
     ~sd_ensemble() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        drop_graphs();
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (cstream) (void)hipStreamDestroy(cstream);
@@ -1757,12 +1811,18 @@ struct sd_ensemble {
 };
 
 namespace {
-// pass indices of one step of an instance, with the fraction of dt of each
-std::vector<std::pair<int, double>> step_passes(const sd_plan_t *p, sd_dtype dt, int order) {
+// group applications of one part (0 prologue, 1 core, 2 epilogue) of a call
+const std::vector<std::pair<int, double>> &part_of(const CallSchedule &cs, int q) {
+    return q == 0 ? cs.pro : q == 1 ? cs.core : cs.epi;
+}
+
+// pass indices of one part of a call of an instance, with the fraction of dt
+// of each
+std::vector<std::pair<int, double>> part_passes(const sd_plan_t *p, sd_dtype dt, int order, int q) {
     std::vector<std::pair<int, double>> out;
     const Program &P = p->prog[dt];
-    const int K = (int)p->groups.size();
-    for (auto &gf : step_schedule(K, order))
+    const CallSchedule cs = call_schedule((int)p->groups.size(), order);
+    for (auto &gf : part_of(cs, q))
         for (int i = P.group_first[gf.first]; i < P.group_first[gf.first + 1]; ++i)
             out.push_back({i, gf.second});
     return out;
@@ -1781,12 +1841,15 @@ extern "C" sd_status sd_ensemble_create(const sd_plan_t *const *plans, int32_t c
             return fail(SD_ERR_ARG, "sd_ensemble_create: null plan");
         }
         e->plans.push_back(plans[i]);
-        // (segment tables for the longest step schedule, order 4's, so that
-        // one workspace serves every order)
-        e->max_levels = std::max<int>(e->max_levels, (int)step_passes(plans[i], dtype, 4).size());
+        // (segment tables for the longest part of any order, so that one
+        // workspace serves every order)
+        for (int order : {1, 2, 4})
+            for (int q = 0; q < kParts; ++q)
+                e->max_levels = std::max<int>(e->max_levels, (int)part_passes(plans[i], dtype, order, q).size());
     }
     e->dtype = dtype;
-    e->ws_needed = ((int64_t)e->max_levels * count * (int64_t)sizeof(MultiSeg) + 255) / 256 * 256;
+    e->part_bytes = ((int64_t)e->max_levels * count * (int64_t)sizeof(MultiSeg) + 255) / 256 * 256;
+    e->ws_needed = kParts * e->part_bytes;
     *out = e;
     return SD_OK;
 }
@@ -1805,10 +1868,7 @@ extern "C" sd_status sd_ensemble_bind_workspace(sd_ensemble *e, void *dev_ptr, s
     if (((uintptr_t)dev_ptr) & 255) return fail(SD_ERR_WORKSPACE, "workspace not 256-byte aligned");
     e->ws = dev_ptr;
     e->ws_bytes = bytes;
-    if (e->exec) {
-        (void)hipGraphExecDestroy(e->exec);
-        e->exec = nullptr;
-    }
+    e->drop_graphs();
     return SD_OK;
 }
 
@@ -1820,33 +1880,40 @@ struct LevelLaunch {
     uint32_t lds;   // largest LDS layout of its segments
 };
 
-// Build and upload the level tables of one step; instances with any tile
-// below the multi-instance kernel's minimum are listed in *small instead.
-sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order,
-                       std::vector<LevelLaunch> *launches, std::vector<int> *small) {
+// instances that run through the single-instance pass launches: any tile
+// below the multi-instance kernel's minimum, or a state above 4 GiB (the
+// multi-instance kernel uses 32-bit in-state offsets)
+std::vector<int> small_instances(const sd_ensemble *e) {
+    std::vector<int> small;
+    const size_t amp = e->dtype == SD_C64 ? sizeof(float2) : sizeof(double2);
+    for (int i = 0; i < (int)e->plans.size(); ++i) {
+        bool is_small = ((uint64_t)amp << e->plans[i]->n) > ((uint64_t)1 << 32);
+        for (const PassHost &ph : e->plans[i]->prog[e->dtype].passes) is_small = is_small || ph.D < kTileMinD;
+        if (is_small) small.push_back(i);
+    }
+    return small;
+}
+
+// Build and upload the level tables of part q of a call into the part's
+// region of the workspace.
+sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order, int q,
+                       const std::vector<int> &small, std::vector<LevelLaunch> *launches) {
     const int n_inst = (int)e->plans.size();
     std::vector<std::vector<std::pair<int, double>>> seq(n_inst);
     std::vector<char> is_small(n_inst, 0);
+    for (int i : small) is_small[i] = 1;
     int levels = 0;
-    small->clear();
     for (int i = 0; i < n_inst; ++i) {
-        seq[i] = step_passes(e->plans[i], e->dtype, order);
-        for (auto &pf : seq[i])
-            if (e->plans[i]->prog[e->dtype].passes[pf.first].D < kTileMinD) is_small[i] = 1;
-        // the multi-instance kernel uses 32-bit in-state offsets
-        const size_t amp = e->dtype == SD_C64 ? sizeof(float2) : sizeof(double2);
-        if (((uint64_t)amp << e->plans[i]->n) > ((uint64_t)1 << 32)) is_small[i] = 1;
-        if (is_small[i]) {
-            small->push_back(i);
-            continue;
-        }
+        if (is_small[i]) continue;
+        seq[i] = part_passes(e->plans[i], e->dtype, order, q);
         levels = std::max<int>(levels, (int)seq[i].size());
     }
     std::vector<MultiSeg> host;
     launches->clear();
+    const int64_t base = (int64_t)q * e->part_bytes;
     for (int l = 0; l < levels; ++l) {
         for (int D = kTileMinD; D <= kMaxTileLog2; ++D) {
-            LevelLaunch L{(int64_t)host.size(), 0, 0, D, false, 0};
+            LevelLaunch L{base + (int64_t)(host.size() * sizeof(MultiSeg)), 0, 0, D, false, 0};
             for (int i = 0; i < n_inst; ++i) {
                 if (is_small[i] || l >= (int)seq[i].size()) continue;
                 const sd_plan_t *p = e->plans[i];
@@ -1870,10 +1937,12 @@ sd_status build_levels(sd_ensemble *e, void *const *states, double dt, int order
             if (L.nseg) launches->push_back(L);
         }
     }
-    if ((int64_t)(host.size() * sizeof(MultiSeg)) > (int64_t)e->ws_bytes)
+    if ((int64_t)(host.size() * sizeof(MultiSeg)) > e->part_bytes ||
+        base + e->part_bytes > (int64_t)e->ws_bytes)
         return fail(SD_ERR_WORKSPACE, "ensemble workspace too small for the segment tables");
     if (host.empty()) return SD_OK;
-    return hip_check(hipMemcpy(e->ws, host.data(), host.size() * sizeof(MultiSeg), hipMemcpyHostToDevice),
+    return hip_check(hipMemcpy((char *)e->ws + base, host.data(), host.size() * sizeof(MultiSeg),
+                               hipMemcpyHostToDevice),
                      "ensemble segment upload");
 }
 
@@ -1881,19 +1950,31 @@ template <typename T>
 sd_status launch_levels(sd_ensemble *e, const std::vector<LevelLaunch> &launches, hipStream_t s) {
     std::call_once(g_once, init_device_props);
     if (g_init_status != SD_OK) return fail(g_init_status, "device initialisation failed");
-    const MultiSeg *dsegs = (const MultiSeg *)e->ws;
     for (auto &L : launches) {
+        const MultiSeg *dsegs = (const MultiSeg *)((const char *)e->ws + L.off);
         const int threads = 1 << (L.D - kLE);
         const int per_cu = blocks_per_cu(L.D);
         const int grid = (int)std::min<int64_t>(L.total, (int64_t)std::max(1, g_num_cu) * per_cu);
         const size_t lds = L.lds;
         if (L.gen)
-            hipLaunchKernelGGL((k_tile_multi<T, true>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
+            hipLaunchKernelGGL((k_tile_multi<T, true>), dim3(grid), dim3(threads), lds, s, dsegs,
                                (int)L.nseg, L.total);
         else
-            hipLaunchKernelGGL((k_tile_multi<T, false>), dim3(grid), dim3(threads), lds, s, dsegs + L.off,
+            hipLaunchKernelGGL((k_tile_multi<T, false>), dim3(grid), dim3(threads), lds, s, dsegs,
                                (int)L.nseg, L.total);
         sd_status r = hip_check(hipGetLastError(), "k_tile_multi launch");
+        if (r != SD_OK) return r;
+    }
+    return SD_OK;
+}
+
+// the single-instance pass launches of part q for one small instance
+sd_status run_small(sd_ensemble *e, int i, void *state, double dt, int order, int q, hipStream_t s) {
+    for (auto &pf : part_passes(e->plans[i], e->dtype, order, q)) {
+        sd_status r = e->dtype == SD_C64 ? launch_pass<float2, 0>(e->plans[i], e->dtype, pf.first, state,
+                                                                  dt * pf.second, s)
+                                         : launch_pass<double2, 0>(e->plans[i], e->dtype, pf.first, state,
+                                                                   dt * pf.second, s);
         if (r != SD_OK) return r;
     }
     return SD_OK;
@@ -1923,41 +2004,38 @@ extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, dou
         if (r != SD_OK) return r;
     }
     std::vector<void *> st(states, states + e->plans.size());
-    // The captured step holds every plan's workspace addresses (its pass
+    // The captured parts hold every plan's workspace addresses (its pass
     // records and term tables): a plan rebound to other memory since then
-    // invalidates it, like new state pointers or another dt or order.
+    // invalidates them, like new state pointers or another dt or order.
     std::vector<const void *> pws(e->plans.size());
     for (size_t i = 0; i < e->plans.size(); ++i) pws[i] = e->plans[i]->ws;
-    if (!(e->exec && e->g_dt == dt && e->g_order == order && e->g_states == st &&
-          e->g_plan_ws == pws)) {
-        if (e->exec) {
-            (void)hipGraphExecDestroy(e->exec);
-            e->exec = nullptr;
-        }
-        if (e->graph) {
-            (void)hipGraphDestroy(e->graph);
-            e->graph = nullptr;
-        }
+    if (!(e->cached && e->g_dt == dt && e->g_order == order && e->g_states == st && e->g_plan_ws == pws)) {
+        e->drop_graphs();
         // no earlier replay may still read the segment tables being replaced
         r = hip_check(hipStreamSynchronize(e->cstream), "ensemble stream sync");
         if (r != SD_OK) return r;
-        std::vector<LevelLaunch> launches;
-        r = build_levels(e, states, dt, order, &launches, &e->g_small);
-        if (r != SD_OK) return r;
-        r = hip_check(hipStreamBeginCapture(e->cstream, hipStreamCaptureModeThreadLocal), "begin capture");
-        if (r != SD_OK) return r;
-        r = e->dtype == SD_C64 ? launch_levels<float2>(e, launches, e->cstream)
-                               : launch_levels<double2>(e, launches, e->cstream);
-        hipGraph_t g = nullptr;
-        sd_status r2 = hip_check(hipStreamEndCapture(e->cstream, &g), "end capture");
-        if (r != SD_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return r;
+        e->g_small = small_instances(e);
+        for (int q = 0; q < kParts; ++q) {
+            std::vector<LevelLaunch> launches;
+            r = build_levels(e, states, dt, order, q, e->g_small, &launches);
+            if (r != SD_OK) return r;
+            if (launches.empty()) continue;
+            r = hip_check(hipStreamBeginCapture(e->cstream, hipStreamCaptureModeThreadLocal), "begin capture");
+            if (r != SD_OK) return r;
+            r = e->dtype == SD_C64 ? launch_levels<float2>(e, launches, e->cstream)
+                                   : launch_levels<double2>(e, launches, e->cstream);
+            hipGraph_t g = nullptr;
+            sd_status r2 = hip_check(hipStreamEndCapture(e->cstream, &g), "end capture");
+            if (r != SD_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return r;
+            }
+            if (r2 != SD_OK) return r2;
+            e->graph[q] = g;
+            r = hip_check(hipGraphInstantiate(&e->exec[q], e->graph[q], nullptr, nullptr, 0), "graph instantiate");
+            if (r != SD_OK) return r;
         }
-        if (r2 != SD_OK) return r2;
-        e->graph = g;
-        r = hip_check(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0), "graph instantiate");
-        if (r != SD_OK) return r;
+        e->cached = true;
         e->g_dt = dt;
         e->g_order = order;
         e->g_states = st;
@@ -1967,14 +2045,22 @@ extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, dou
     if (r != SD_OK) return r;
     r = hip_check(hipStreamWaitEvent(e->cstream, e->ev_in, 0), "stream wait");
     if (r != SD_OK) return r;
-    for (int64_t k = 0; k < steps; ++k) {
-        r = hip_check(hipGraphLaunch(e->exec, e->cstream), "graph launch");
-        if (r != SD_OK) return r;
-        for (int i : e->g_small) {
-            r = sd_evolve(e->plans[i], states[i], e->dtype, dt, 1, order, e->cstream);
-            if (r != SD_OK) return r;
+    // prologue, core x (steps - 1), epilogue
+    auto part = [&](int q) -> sd_status {
+        if (e->exec[q]) {
+            sd_status rr = hip_check(hipGraphLaunch(e->exec[q], e->cstream), "graph launch");
+            if (rr != SD_OK) return rr;
         }
-    }
+        for (int i : e->g_small) {
+            sd_status rr = run_small(e, i, states[i], dt, order, q, e->cstream);
+            if (rr != SD_OK) return rr;
+        }
+        return SD_OK;
+    };
+    r = part(0);
+    for (int64_t k = 1; k < steps && r == SD_OK; ++k) r = part(1);
+    if (r == SD_OK) r = part(2);
+    if (r != SD_OK) return r;
     r = hip_check(hipEventRecord(e->ev_out, e->cstream), "event record");
     if (r != SD_OK) return r;
     return hip_check(hipStreamWaitEvent(user, e->ev_out, 0), "stream wait");

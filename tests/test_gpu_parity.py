@@ -257,7 +257,9 @@ def test_ensemble_of_uneven_instances(dtype, shrink):
     sd.sd_ensemble_evolve(ens, states, 0.05, 12, 2)
     sd.sd_ensemble_evolve(ens, states, 0.05, 8, 2)   # graph replay path
     for p, s in zip(plans, singles):
-        p.evolve(s, 0.05, 20, 2)
+        # (the same calls: a call joins the G_0 halves of its own steps)
+        p.evolve(s, 0.05, 12, 2)
+        p.evolve(s, 0.05, 8, 2)
     torch.cuda.synchronize()
     for m, s, s1 in zip(models, states, singles):
         got = s.cpu().numpy().astype(np.complex128)
@@ -295,7 +297,8 @@ def test_ensemble_after_plan_rebind(shrink):
     sd.sd_bind_workspace(other.p, old)
     sd.sd_ensemble_evolve(ens, states, 0.05, 6, 2)
     for p, s in zip(plans, singles):
-        p.evolve(s, 0.05, 10, 2)
+        p.evolve(s, 0.05, 4, 2)
+        p.evolve(s, 0.05, 6, 2)
     torch.cuda.synchronize()
     for m, s, s1 in zip(models, states, singles):
         assert torch.equal(s, s1), m.n
