@@ -223,7 +223,9 @@ def ensemble_experiment(args, torch, workloads, sd):
     dt, order = models[0].dt, models[0].order
     log(f"ensemble: planning {len(models)} instances")
     t0 = time.time()
-    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind("cuda") for m in models]
+    o = sd.sd_plan_options_default()
+    o.tile_shrink_c64 = args.tile_shrink
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs, o).bind("cuda") for m in models]
     plan_s = time.time() - t0
     amps = sum(1 << m.n for m in models)
 
@@ -291,7 +293,7 @@ def ensemble_experiment(args, torch, workloads, sd):
            "config": {"workload": "xxz_open_ensemble_256", "instances": len(models),
                       "n_range": [min(m.n for m in models), max(m.n for m in models)],
                       "amplitudes": amps, "order": order, "dt": dt, "seed": 4},
-           "plan_seconds": round(plan_s, 2), **res,
+           "plan_seconds": round(plan_s, 2), "tile_shrink_c64": args.tile_shrink, **res,
            "accuracy_c64_vs_c128": {"steps": args.warmup + args.steps,
                                     "mean_1_minus_F": float(1.0 - np.mean(fids)),
                                     "max_1_minus_F": float(1.0 - np.min(fids))}}
@@ -421,6 +423,9 @@ def main():
     ap.add_argument("--termwise-sample", type=int, default=0,
                     help="sweeps: time the term-by-term step on its first K terms and scale "
                          "by m/K (every term is one rotation pass of the same cost)")
+    ap.add_argument("--tile-shrink", type=int, default=1,
+                    help="ensemble: plans' tile_shrink_c64 (1: smallest tile per complex64 "
+                         "pass, 0: one tile size per plan)")
     ap.add_argument("--nmin", type=int, default=12)
     ap.add_argument("--nmax", type=int, default=30)
     ap.add_argument("--calib-copy", action="store_true",
