@@ -576,6 +576,31 @@ sd_status plan_rounds(PassHost *ps) {
     for (int r = 0; r < nrounds; ++r)
         quads.push_back({p.lanes_post[r][0], p.lanes_post[r][1], p.lanes_post[r][2], p.lanes_post[r][3]});
     if (p.staged) quads.push_back({p.mr[0], p.mr[1], p.mr[2], p.mr[3]});
+    // A round before the Lambda round writes its outputs at its layout XOR a
+    // per-thread flip of its chunk coordinates (the CZs with later chunks):
+    // bit a of the flip is the parity of B[a] & later[r] & (the thread's
+    // coordinates), linear in the lane bits, so lane i's write vector is
+    // lanes_post[r][i] XOR flip(lanes[r][i]).  Those layouts take the same
+    // conflict rules.
+    for (int r = 0; r + 1 < nrounds; ++r) {
+        std::vector<int> chunk;
+        for (int l = 0; l < RB; ++l)
+            if ((p.bmask[r] >> l) & 1u) chunk.push_back(p.reg[r][l]);
+        for (int x = 0; x < p.nx[r]; ++x) chunk.push_back(p.xl[r][x]);
+        auto flip = [&](uint32_t v) {
+            uint32_t f = 0;
+            for (int a : chunk) f |= (uint32_t)(popc(p.B[a] & p.later[r] & v) & 1) << a;
+            return f;
+        };
+        std::array<uint32_t, 4> q;
+        bool any = false;
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t f = i < (int)p.lanes[r].size() ? flip(p.lanes[r][i]) : 0;
+            any = any || f;
+            q[i] = p.lanes_post[r][i] ^ f;
+        }
+        if (any) quads.push_back(q);
+    }
     auto lowbits = [](uint32_t v, const uint32_t *m, int nb) {
         uint32_t g = v & ((1u << nb) - 1);
         for (int j = 0; j < nb; ++j) g ^= (uint32_t)(popc(v & m[j]) & 1) << j;
