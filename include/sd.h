@@ -378,7 +378,11 @@ sd_status sd_inner_noalloc(const void *a, const void *b, sd_dtype dtype, int32_t
 /* Ensemble of independent instances (uneven sizes allowed), evolved together.
    plans: `count` plans, each with a bound workspace; states: host array of
    `count` device pointers.  One launch per pass level (and tile size) per
-   step; one step is captured once as a HIP graph and replayed.
+   step over the tiles of every instance; instances with tiles below 2^10
+   or states above 4 GiB take their own pass launches after those.  A step
+   is captured once as one HIP graph and replayed (a call: prologue, core
+   step x (steps - 1), epilogue, where group applications joined across
+   steps differ).
    sd_ensemble_workspace_bytes: the device bytes for the per-level segment
    tables, enough for every order (1, 2, 4); the caller allocates them
    (256-byte aligned) and binds them with sd_ensemble_bind_workspace before

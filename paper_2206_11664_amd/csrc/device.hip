@@ -1792,7 +1792,7 @@ struct sd_ensemble {
     int g_order = 0;
     std::vector<void *> g_states;
     std::vector<const void *> g_plan_ws;  // each plan's workspace when the graphs were built
-    std::vector<int> g_small;   // instances run through sd_evolve's pass launches instead
+    std::vector<int> g_small;   // instances run by single-instance pass launches (in the same graphs)
     void drop_graphs() {
         for (int q = 0; q < kParts; ++q) {
             if (exec[q]) (void)hipGraphExecDestroy(exec[q]);
@@ -2019,11 +2019,17 @@ extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, dou
             std::vector<LevelLaunch> launches;
             r = build_levels(e, states, dt, order, q, e->g_small, &launches);
             if (r != SD_OK) return r;
-            if (launches.empty()) continue;
+            bool small_work = false;
+            for (int i : e->g_small) small_work = small_work || !part_passes(e->plans[i], e->dtype, order, q).empty();
+            if (launches.empty() && !small_work) continue;
+            // one graph per part: the level launches, then the pass launches
+            // of the instances outside them
             r = hip_check(hipStreamBeginCapture(e->cstream, hipStreamCaptureModeThreadLocal), "begin capture");
             if (r != SD_OK) return r;
             r = e->dtype == SD_C64 ? launch_levels<float2>(e, launches, e->cstream)
                                    : launch_levels<double2>(e, launches, e->cstream);
+            for (size_t k = 0; k < e->g_small.size() && r == SD_OK; ++k)
+                r = run_small(e, e->g_small[k], states[e->g_small[k]], dt, order, q, e->cstream);
             hipGraph_t g = nullptr;
             sd_status r2 = hip_check(hipStreamEndCapture(e->cstream, &g), "end capture");
             if (r != SD_OK) {
@@ -2047,15 +2053,8 @@ extern "C" sd_status sd_ensemble_evolve(sd_ensemble *e, void *const *states, dou
     if (r != SD_OK) return r;
     // prologue, core x (steps - 1), epilogue
     auto part = [&](int q) -> sd_status {
-        if (e->exec[q]) {
-            sd_status rr = hip_check(hipGraphLaunch(e->exec[q], e->cstream), "graph launch");
-            if (rr != SD_OK) return rr;
-        }
-        for (int i : e->g_small) {
-            sd_status rr = run_small(e, i, states[i], dt, order, q, e->cstream);
-            if (rr != SD_OK) return rr;
-        }
-        return SD_OK;
+        if (!e->exec[q]) return SD_OK;
+        return hip_check(hipGraphLaunch(e->exec[q], e->cstream), "graph launch");
     };
     r = part(0);
     for (int64_t k = 1; k < steps && r == SD_OK; ++k) r = part(1);

@@ -269,6 +269,38 @@ def test_ensemble_of_uneven_instances(dtype, shrink):
     sd.sd_ensemble_destroy(ens)
 
 
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_ensemble_of_small_instances_only(dtype):
+    # every instance below the multi-instance kernel's tile minimum: the step
+    # graphs hold only single-instance pass launches; a second call with the
+    # same arguments replays them, a third with another dt captures again
+    models = workloads.xxz_ensemble(count=3, seed=11, nmin=6, nmax=9, steps=10)
+    print(f"[gpu] small-only ensemble sizes {[m.n for m in models]} dtype={dtype}", flush=True)
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in models]
+    ens = sd.sd_ensemble_create([p.p for p in plans], dtype)
+    ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+    sd.sd_ensemble_bind_workspace(ens, ws)
+    psi0 = [workloads.random_state(m.n, 80 + i) for i, m in enumerate(models)]
+    states = [torch.from_numpy(a).to(TDT[dtype]).cuda() for a in psi0]
+    singles = [s.clone() for s in states]
+    calls = [(0.05, 4), (0.05, 3), (0.03, 2)]
+    for dt, k in calls:
+        sd.sd_ensemble_evolve(ens, states, dt, k, 2)
+    for p, s in zip(plans, singles):
+        for dt, k in calls:
+            p.evolve(s, dt, k, 2)
+    torch.cuda.synchronize()
+    for i, (m, s, s1) in enumerate(zip(models, states, singles)):
+        assert torch.equal(s, s1), m.n
+        want = psi0[i]
+        for dt, k in calls:
+            want = oracle.evolve(m.n, m.paulis, m.coeffs, want, dt, k, 2)
+        err = l2(s.cpu().numpy().astype(np.complex128), want)
+        print(f"[gpu]   instance {i} n={m.n}: L2 {err:.3e}", flush=True)
+        assert err <= TOL[dtype], (m.n, err)
+    sd.sd_ensemble_destroy(ens)
+
+
 @pytest.mark.parametrize("shrink", [1, 0])
 def test_ensemble_after_plan_rebind(shrink):
     # a member plan rebound to a new workspace (the old one released) between
