@@ -502,7 +502,8 @@ __device__ __forceinline__ void from_c128(double2 &o, double2 v) { o = v; }
 // One tile pass over tiles t0, t0 + stride, ... < t1 of the pass `pdp` (the
 // whole pass when called with blockIdx.x, n_tiles, gridDim.x).  MODE 0
 // evolves in place, MODE 1 adds this block's share of <psi|H_pass|psi> to
-// acc.  OFF is the type of in-state byte offsets: uint32_t when the state is
+// acc[0], MODE 2 this wave's share of <psi|P_k|psi> for every term k of the
+// pass to lane k mod 64's acc[k / 64].  OFF is the type of in-state byte offsets: uint32_t when the state is
 // at most 4 GiB, else uint64_t.  GEN admits chunks of fewer than kLE span
 // coordinates in rounds other than Lambda's; without it those rounds are
 // straight-line code (four plain butterfly stages between one LDS read and
@@ -515,7 +516,7 @@ __device__ __forceinline__ void from_c128(double2 &o, double2 v) { o = v; }
 template <typename T, int MODE, typename OFF, bool GEN, typename PDP = const PassDev *>
 __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict__ pdp,
                                           const uint8_t *__restrict__ ws, double tau, int64_t t0,
-                                          int64_t t1, int64_t stride, double &acc) {
+                                          int64_t t1, int64_t stride, double (&acc)[4]) {
     constexpr bool FULL = sizeof(T) == 16;
     // complex128 tiles and the general round code skip the register
     // prefetch of the next tile: it would not fit two waves per SIMD
@@ -560,7 +561,11 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
             trec[k] = make_double2(0.0, __longlong_as_double((long long)z));
             // (evolution: the coefficient times -tau, so that the bucket
             // sums are the phase angles themselves)
-            tsrc[k] = make_double2(MODE == 0 ? -tau * cf : cf, __longlong_as_double((long long)zt));
+            // (term values: the sign (-1)^{r_k} i^{e_k} alone, without c_k)
+            const double v = MODE == 0 ? -tau * cf
+                             : MODE == 1 ? cf
+                                         : ((const double *)(tb + o2 + 16 * (int64_t)m))[k];
+            tsrc[k] = make_double2(v, __longlong_as_double((long long)zt));
         }
     }
     const double scale = pd.scale;
@@ -952,7 +957,41 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
                     }
             if (MODE == 1) {
 #pragma unroll
-                for (int j = 0; j < kE; ++j) acc += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
+                for (int j = 0; j < kE; ++j) acc[0] += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
+                __syncthreads();
+                break;
+            }
+            if (MODE == 2) {
+                // term k of bucket w: its sign times sum_j |psi_j|^2
+                // (-1)^{w.j} (a kE-point Walsh-Hadamard of the thread's
+                // probabilities), summed over the wave; lane k mod 64 keeps
+                // the running total
+                double W[kE];
+#pragma unroll
+                for (int j = 0; j < kE; ++j) W[j] = (re[j] * re[j] + im[j] * im[j]) * scale;
+#pragma unroll
+                for (int b = 0; b < kLE; ++b)
+#pragma unroll
+                    for (int j = 0; j < kE; ++j)
+                        if (!((j >> b) & 1)) {
+                            const double a0 = W[j], a1 = W[j | (1 << b)];
+                            W[j] = a0 + a1;
+                            W[j | (1 << b)] = a0 - a1;
+                        }
+                const int lane = (int)(tid & 63u);
+#pragma unroll
+                for (int w = 0; w < kE; ++w) {
+                    for (int k = bk[w]; k < bk[w + 1]; ++k) {
+                        const double2 rec = trec[k];
+                        const uint32_t z = (uint32_t)__double_as_longlong(rec.y);
+                        const uint64_t flip = (uint64_t)__popc(z & sgnb) << 63;
+                        double v = __longlong_as_double((long long)((uint64_t)__double_as_longlong(rec.x) ^ flip)) * W[w];
+                        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if ((k >> 6) == q && lane == (k & 63)) acc[q] += v;
+                    }
+                }
                 __syncthreads();
                 break;
             }
@@ -1065,14 +1104,32 @@ template <typename T, int MODE, typename OFF, bool GEN>
 __global__ void __launch_bounds__(kMaxThreads)
 k_tile(T *__restrict__ state, const PassDev *__restrict__ pdp, const uint8_t *__restrict__ ws,
        double tau, double *__restrict__ partial) {
-    double acc = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     tile_pass<T, MODE, OFF, GEN>(state, pdp, ws, tau, blockIdx.x, pdp->n_tiles, gridDim.x, acc);
+    extern __shared__ double2 lds_dyn[];
     if (MODE == 1) {
-        extern __shared__ double2 lds_dyn[];
         const int nrounds = pdp->nr > 0 ? pdp->nr : 1;
         double *red = (double *)((char *)lds_dyn + tile_lds(pdp->D, blockDim.x, nrounds, pdp->m).red);
-        const double s2 = block_sum_waves(acc, red);
+        const double s2 = block_sum_waves(acc[0], red);
         if (threadIdx.x == 0) partial[blockIdx.x] += s2;
+    }
+    if (MODE == 2) {
+        // per-wave totals of the pass's terms through the (now free) tile
+        // area of LDS (2^(D-10) waves x kMaxPassTerms doubles = 2^(D+1)
+        // bytes of its 2^(D+4)), then the block's total of term k into
+        // partial[block * kMaxPassTerms + k]
+        double *red = (double *)lds_dyn;
+        const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63u);
+        const int nw = (int)(blockDim.x >> 6), m = pdp->m;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wave * kMaxPassTerms + q * 64 + lane] = acc[q];
+        __syncthreads();
+        for (int k = (int)threadIdx.x; k < m; k += (int)blockDim.x) {
+            double s2 = 0.0;
+            for (int w = 0; w < nw; ++w) s2 += red[w * kMaxPassTerms + k];
+            partial[(int64_t)blockIdx.x * kMaxPassTerms + k] = s2;
+        }
     }
 }
 
@@ -1101,7 +1158,7 @@ __global__ void __launch_bounds__(kMaxThreads)
 k_tile_multi(const MultiSeg *__restrict__ segs, int nseg, int64_t total) {
     const int64_t lo = (total * (int64_t)blockIdx.x) / gridDim.x;
     const int64_t hi = (total * (int64_t)(blockIdx.x + 1)) / gridDim.x;
-    double acc = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < nseg; ++i) {
         const MultiSeg sg = segs[i];
         const int64_t a = sg.first_item, b = sg.first_item + sg.n_tiles;
@@ -1152,14 +1209,22 @@ k_inner(const T *__restrict__ a, const T *__restrict__ b, int64_t dim,
 }
 
 // per-term totals of MODE 2: out[k] = sum over blocks b < count of
-// partial[b * kMaxPassTerms + k], in block order
-__global__ void k_term_final(const double *__restrict__ partial, int count, int m,
-                             double *__restrict__ out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
+// partial[b * kMaxPassTerms + k] in a fixed order.  A block takes 64 terms
+// (one per lane, so that a wave reads 64 neighbouring values of one block's
+// row); wave q of the 4 adds rows q, q + 4, ..., and the four wave sums are
+// added in wave order.
+constexpr int kTermFinalThreads = 256;
+__global__ void __launch_bounds__(kTermFinalThreads)
+k_term_final(const double *__restrict__ partial, int count, int m, double *__restrict__ out) {
+    __shared__ double red[kTermFinalThreads];
+    const int lane = (int)(threadIdx.x & 63u), q = (int)(threadIdx.x >> 6);
+    const int k = (int)blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int b = 0; b < count; ++b) s += partial[(int64_t)b * kMaxPassTerms + k];
-    out[k] = s;
+    if (k < m)
+        for (int b = q; b < count; b += kTermFinalThreads / 64) s += partial[(int64_t)b * kMaxPassTerms + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (q == 0 && k < m) out[k] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
 }
 
 // final sum of `count` interleaved groups of `width` (1 or 2) partials in a
@@ -1247,6 +1312,10 @@ static void init_device_props() {
     prep(k_tile<double2, 0, uint64_t, false>);
     prep(k_tile<double2, 0, uint64_t, true>);
     prep(k_tile<float2, 1, uint32_t, true>);
+    prep(k_tile<float2, 2, uint32_t, true>);
+    prep(k_tile<double2, 2, uint32_t, true>);
+    prep(k_tile<float2, 2, uint64_t, true>);
+    prep(k_tile<double2, 2, uint64_t, true>);
     prep(k_tile<double2, 1, uint32_t, true>);
     prep(k_tile<float2, 1, uint64_t, true>);
     prep(k_tile<double2, 1, uint64_t, true>);
@@ -1498,17 +1567,43 @@ extern "C" sd_status sd_term_expectations(const sd_plan_t *p, const void *state,
         if (ph.D > kMaxTileLog2 || m > kMaxPassTerms)
             return fail(SD_ERR_INTERNAL, "pass exceeds the on-chip tile limits");
         const PassDev *pd = (const PassDev *)(ws + p->ws_off_prog[dtype] + (int64_t)i * sizeof(PassDev));
-        const int grid = (int)std::min<int64_t>((int64_t)1 << (p->n - ph.D), kTermGrid);
-        const size_t lds = (size_t)16 << ph.D;
-        if (dtype == SD_C64)
-            hipLaunchKernelGGL((k_pass<float2, 2>), dim3(grid), dim3(kBlock), lds, s, (float2 *)state, pd,
-                               ws, 0.0, partial);
-        else
-            hipLaunchKernelGGL((k_pass<double2, 2>), dim3(grid), dim3(kBlock), lds, s, (double2 *)state,
-                               pd, ws, 0.0, partial);
-        sd_status r = hip_check(hipGetLastError(), "k_pass (terms) launch");
+        int grid = (int)std::min<int64_t>((int64_t)1 << (p->n - ph.D), kTermGrid);
+        if (ph.D >= kTileMinD && !g_generic) {
+            // as many blocks as fit the CUs at once (several per CU for
+            // tiles below 2^13)
+            grid = std::min(grid, std::max(1, g_num_cu) * blocks_per_cu(ph.D));
+            // the tile kernel's forward rounds, then per-term sums in the
+            // Lambda round (the general round code, as for the expectation)
+            const int threads = 1 << (ph.D - kLE);
+            const size_t lds_tile = tile_lds(ph.D, threads, std::max(ph.nr, 1), m).total;
+            const bool narrow = ((uint64_t)(dtype == SD_C64 ? sizeof(float2) : sizeof(double2)) << p->n) <=
+                                ((uint64_t)1 << 32);
+            void *st = const_cast<void *>(state);
+            if (dtype == SD_C64 && narrow)
+                hipLaunchKernelGGL((k_tile<float2, 2, uint32_t, true>), dim3(grid), dim3(threads), lds_tile, s,
+                                   (float2 *)st, pd, ws, 0.0, partial);
+            else if (dtype == SD_C64)
+                hipLaunchKernelGGL((k_tile<float2, 2, uint64_t, true>), dim3(grid), dim3(threads), lds_tile, s,
+                                   (float2 *)st, pd, ws, 0.0, partial);
+            else if (narrow)
+                hipLaunchKernelGGL((k_tile<double2, 2, uint32_t, true>), dim3(grid), dim3(threads), lds_tile, s,
+                                   (double2 *)st, pd, ws, 0.0, partial);
+            else
+                hipLaunchKernelGGL((k_tile<double2, 2, uint64_t, true>), dim3(grid), dim3(threads), lds_tile, s,
+                                   (double2 *)st, pd, ws, 0.0, partial);
+        } else {
+            const size_t lds = (size_t)16 << ph.D;
+            if (dtype == SD_C64)
+                hipLaunchKernelGGL((k_pass<float2, 2>), dim3(grid), dim3(kBlock), lds, s, (float2 *)state, pd,
+                                   ws, 0.0, partial);
+            else
+                hipLaunchKernelGGL((k_pass<double2, 2>), dim3(grid), dim3(kBlock), lds, s, (double2 *)state,
+                                   pd, ws, 0.0, partial);
+        }
+        sd_status r = hip_check(hipGetLastError(), "term expectation pass launch");
         if (r != SD_OK) return r;
-        hipLaunchKernelGGL(k_term_final, dim3((m + 255) / 256), dim3(256), 0, s, partial, grid, m, res + off);
+        hipLaunchKernelGGL(k_term_final, dim3((m + 63) / 64), dim3(kTermFinalThreads), 0, s, partial, grid, m,
+                           res + off);
         r = hip_check(hipGetLastError(), "term reduce");
         if (r != SD_OK) return r;
         off += m;

@@ -6,7 +6,7 @@ namespace sd {
 
 constexpr int kMaxD = 16;            // tile dims a record can describe
 constexpr int kMaxPassTerms = 256;   // Lambda terms per pass (LDS budget)
-constexpr int kTermGrid = 256;       // blocks of a per-term expectation pass
+constexpr int kTermGrid = 2048;      // blocks of a per-term expectation pass (at most)
 
 struct alignas(256) PassDev {
     int32_t n;          // qubits

@@ -622,7 +622,7 @@ def test_syk_majorana_modes(n, mode, dtype):
     check(m, dtype, m.dt, 2, 1, dict(mode=mode), psi0=m.initial_state())
 
 
-@pytest.mark.parametrize("case", ["klocal", "tfim", "syk", "jw", "wide"])
+@pytest.mark.parametrize("case", ["klocal", "tfim", "syk", "jw", "wide", "dense", "shifted"])
 @pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
 def test_term_expectations_match_oracle(case, dtype):
     # grouped measurement: <psi|P_k|psi> of every term from one transform per
@@ -634,6 +634,12 @@ def test_term_expectations_match_oracle(case, dtype):
         "syk": (workloads.syk_majorana(6), {}),
         "jw": (workloads.jw_fermionic(n=11, total=150), dict(tile_log2_c64=10, tile_log2_c128=10)),
         "wide": (workloads.random_klocal(n=16, m=300, seed=43, init_seed=44), {}),
+        # a diagonal pass of 120 terms (lanes hold the running sums of
+        # terms k mod 64, a second register from term 64 on)
+        "dense": (workloads.tfim_fully_connected(16), {}),
+        # 2^10 tiles: shifted round 0 and a CZ between register slots
+        "shifted": (workloads.random_klocal(n=12, m=300, seed=3, init_seed=2),
+                    dict(tile_log2_c64=10, tile_log2_c128=10)),
     }[case]
     o = sd.sd_plan_options_default()
     for k, v in opts.items():
@@ -649,6 +655,30 @@ def test_term_expectations_match_oracle(case, dtype):
     print(f"[gpu] term expectations {case} dtype={dtype} terms={len(want)} max err {err:.2e}", flush=True)
     assert err <= (1e-12 if dtype == sd.SD_C128 else 1e-6)
     assert abs(float(np.dot(t.c, got)) - plan.expectation(d)) <= 1e-9
+
+
+@pytest.mark.parametrize("dtype", [sd.SD_C128, sd.SD_C64])
+def test_term_expectations_sampled_n24(dtype):
+    # n = 24 (passes of up to 3 rounds, the tile kernel's per-term sums over
+    # 4096 tiles): 32 sampled terms against the oracle on the same state,
+    # and the weighted sum of all of them against sd_expectation
+    m = workloads.random_klocal(n=24, m=1500, seed=3, init_seed=2)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    psi = workloads.random_state(24, 46)
+    d = torch.from_numpy(psi).to(TDT[dtype]).cuda()
+    got = plan.term_expectations(d)
+    ref_state = d.cpu().numpy().astype(np.complex128)
+    t = oracle.build_terms(m.n, m.paulis, m.coeffs)
+    ids = np.sort(np.random.default_rng(47).choice(len(t.x), size=32, replace=False))
+    sub = oracle.Terms(t.n, t.x[ids], t.z[ids], t.c[ids], t.source[ids])
+    want = oracle.term_expectations(m.n, None, None, ref_state, terms=sub)
+    err = float(np.abs(got[ids] - want).max())
+    e = plan.expectation(d)
+    print(f"[gpu] term expectations n=24 dtype={dtype}: {len(t.x)} terms, sampled max err {err:.2e}, "
+          f"sum c_k <P_k> - E {float(np.dot(t.c, got)) - e:.2e}", flush=True)
+    assert err <= (1e-12 if dtype == sd.SD_C128 else 1e-6)
+    assert abs(float(np.dot(t.c, got)) - e) <= 1e-9
+    plan.close()
 
 
 def test_term_expectations_time_series():
