@@ -10,7 +10,9 @@ the fidelity figure.
 
 Prints one JSON line on stdout; progress goes to stderr.  --experiment
 tfim_sweep | syk_sweep runs the paper's two experiments instead (one line per
-n); --experiment ensemble the 256-instance XXZ ensemble (one line).
+n); --experiment ensemble the 256-instance XXZ ensemble, xxz26 / jw32 the
+XXZ chain at n = 26 and the Jordan-Wigner workload at n = 32, observables the
+per-term expectation values of the benchmark Hamiltonian (one line each).
 """
 import argparse
 import collections
@@ -397,6 +399,66 @@ def config_experiment(args, torch, workloads, sd):
     print(json.dumps(out), flush=True)
 
 
+def observables_experiment(args, torch, workloads, sd):
+    """Grouped measurement on this GPU: <psi|P_k|psi> of every term of the
+    n = 28 random k-local benchmark Hamiltonian (1932 terms) from one
+    forward transform per (sub-)group pass, complex64 and complex128 states
+    (a random state drawn on the GPU).  Timed (host clock around the
+    synchronising call, median of --steps calls after one warm-up): the
+    per-term call, the energy call and one first-order evolve step.  Read
+    bytes: one read of the state per pass.  Check: sum_k c_k <P_k> against
+    the energy call (a different reduction of the same passes)."""
+    import numpy as np
+    n = args.n
+    m = workloads.random_klocal(n=n)
+    plan = sd.Plan(n, m.paulis, m.coeffs).bind("cuda")
+    info = plan.info
+    coef = np.asarray(sd.sd_hamiltonian_terms(plan.h)[3], dtype=np.float64)   # merged-term c_k
+    res = {}
+    for name, tdt, B, passes in (("c64", torch.complex64, 8, int(info.passes_c64)),
+                                 ("c128", torch.complex128, 16, int(info.passes_c128))):
+        st = torch.empty(1 << n, dtype=tdt, device="cuda")
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        flat = torch.view_as_real(st).view(-1)
+        for i in range(0, flat.numel(), 1 << 28):
+            flat[i:i + (1 << 28)].normal_(generator=gen)
+        del flat
+        st /= sd.sd_norm2(st, n) ** 0.5
+        vals = plan.term_expectations(st)
+        e = plan.expectation(st)
+        tt, te = [], []
+        for _ in range(max(3, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vals = plan.term_expectations(st)
+            t1 = time.perf_counter()
+            e = plan.expectation(st)
+            te.append(time.perf_counter() - t1)
+            tt.append(t1 - t0)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        plan.evolve(st, m.dt, 1, 1)
+        ev1.record()
+        torch.cuda.synchronize()
+        sec = float(np.median(tt))
+        rd = passes * (1 << n) * B
+        res[name] = {"term_expectations_ms": round(1e3 * sec, 2),
+                     "expectation_ms": round(1e3 * float(np.median(te)), 2),
+                     "evolve_step_ms": round(ev0.elapsed_time(ev1), 2),
+                     "terms_per_s": round(len(vals) / sec, 1), "passes": passes,
+                     "read_bytes": rd, "read_gbps": round(rd / sec / 1e9, 1),
+                     "sum_c_k_P_k_minus_energy": float(np.dot(coef, vals) - e)}
+        log(f"observables {name}: {res[name]}")
+        del st
+    out = {"experiment": "observables", "metric": "per-term expectation values of H (grouped measurement)",
+           "unit": "terms/s", "config": {"workload": f"random_klocal_n{n}", "n_qubits": n,
+                                         "terms": int(info.n_terms), "groups": int(info.n_groups)},
+           "calls_timed": max(3, args.steps), **res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,12 +468,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference-modes", action="store_true")
     ap.add_argument("--cpu-sample-terms", type=int, default=128)
-    ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep", "ensemble", "xxz26", "jw32"],
+    ap.add_argument("--experiment", choices=["tfim_sweep", "syk_sweep", "ensemble", "xxz26", "jw32",
+                                             "observables"],
                     default=None,
                     help="instead of the benchmark line: the paper's fully connected TFIM "
                          "or SYK Majorana sweep, grouped vs term by term (one JSON line per n), "
-                         "the 256-instance XXZ ensemble, the XXZ chain at n = 26 or the "
-                         "Jordan-Wigner workload at n = 32 (one JSON line each)")
+                         "the 256-instance XXZ ensemble, the XXZ chain at n = 26, the "
+                         "Jordan-Wigner workload at n = 32 or the per-term expectation "
+                         "values of the benchmark Hamiltonian (one JSON line each)")
     ap.add_argument("--nstep", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true",
                     help="plan with the default tile sizes (2^13) instead of autotuning them; "
@@ -449,6 +513,9 @@ def main():
         return
     if args.experiment in ("xxz26", "jw32"):
         config_experiment(args, torch, workloads, sd)
+        return
+    if args.experiment == "observables":
+        observables_experiment(args, torch, workloads, sd)
         return
     if args.experiment:
         paper_sweep(args, torch, workloads, sd)
