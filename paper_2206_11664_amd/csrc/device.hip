@@ -872,9 +872,9 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
     // directions are the same code.  Step 0 of a direct pass finds its input
     // in re/im already and its last step leaves the results there.  Every
     // step ends with a block barrier.
-    auto transform = [&](OFF xb) {
-        const int total = nr > 0 ? 2 * nr - 1 : 1;
-        for (int step = 0; step < total; ++step) {
+    // One step of the tile's rounds (step `step` of `total`); true when
+    // the expectation modes are done with the tile.
+    auto one_step = [&](const int step, const int total) -> bool {
             const int r = step < nrounds ? step : 2 * nr - 2 - step;
             const bool lam = step == nrounds - 1;
             const bool fwd = step < nrounds - 1;
@@ -915,7 +915,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
                 if (sh0 && step == 0) apply_sign0(ab.x);
                 if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
                 __syncthreads();
-                continue;
+                return false;
             }
             const bool tw = pd.iflag[r] & 1u;
             if (czm) apply_cz(czm);
@@ -959,7 +959,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
 #pragma unroll
                 for (int j = 0; j < kE; ++j) acc[0] += (re[j] * re[j] + im[j] * im[j]) * A[j] * scale;
                 __syncthreads();
-                break;
+                return true;
             }
             if (MODE == 2) {
                 // term k of bucket w: its sign times sum_j |psi_j|^2
@@ -993,7 +993,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
                     }
                 }
                 __syncthreads();
-                break;
+                return true;
             }
             // (no double-angle steps is the common case: its own loop keeps
             // the halving loop out of the per-amplitude code)
@@ -1028,7 +1028,17 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
             if (czm) apply_cz(czm);
             if (!last || staged) write16(wa, rout);  // (else: results stay in re/im)
             __syncthreads();
-        }
+            return false;
+    };
+    // Step 0 is peeled off the loop: only it can take its input from
+    // registers (a direct pass's round 0), every later step reads its input
+    // from LDS, so the loop carries no register tile from one step to the
+    // next.
+    auto transform = [&](OFF xb) {
+        const int total = nr > 0 ? 2 * nr - 1 : 1;
+        if (!one_step(0, total))
+            for (int step = 1; step < total; ++step)
+                if (one_step(step, total)) break;
         // a direct pass's results: stored here without the prefetch, else at
         // the top of the next tile (see below)
         if (MODE == 0 && !staged && !PF) store16(xb);
