@@ -3,7 +3,8 @@ accuracy bar after 1000 steps of the n = 28 random k-local benchmark, the
 Jordan-Wigner workload's full term mix against the oracle at n = 20, and one
 whole second-order step of it at n = 32 (32 GiB complex64 against the 64 GiB
 complex128 path, 64-bit in-state offsets), with sampled cosets of its widest
-group against the oracle.
+group against the oracle; per-term expectation values at n = 29 in
+complex128 (an 8 GiB state: 64-bit in-state offsets) on sampled terms.
 
 The complex128 path is the FP64 reference where the oracle cannot run at full
 size: it is pinned to the oracle in the same tests on the same generators at
@@ -226,3 +227,28 @@ def test_config5_jw_n32_full_step_c64_vs_c128():
     del s64, s128
     plan.close()
     torch.cuda.empty_cache()
+
+
+def test_term_expectations_n29_wide_offsets():
+    # n = 29, complex128 (8 GiB: the per-term and energy kernels with 64-bit
+    # in-state offsets): 12 sampled terms against the oracle on the same
+    # state, and sum_k c_k <P_k> against sd_expectation
+    n = 29
+    m = workloads.random_klocal(n=n, m=400, seed=5, init_seed=6)
+    plan = sd.Plan(m.n, m.paulis, m.coeffs).bind()
+    psi = _random_state_gpu(n, 48, torch.complex128)
+    got = plan.term_expectations(psi)
+    e = plan.expectation(psi)
+    host = psi.cpu().numpy()
+    del psi
+    torch.cuda.empty_cache()
+    t = oracle.build_terms(m.n, m.paulis, m.coeffs)
+    ids = np.sort(np.random.default_rng(49).choice(len(t.x), size=12, replace=False))
+    sub = oracle.Terms(t.n, t.x[ids], t.z[ids], t.c[ids], t.source[ids])
+    want = oracle.term_expectations(m.n, None, None, host, terms=sub)
+    err = float(np.abs(got[ids] - want).max())
+    print(f"[gpu] term expectations n=29 complex128: {len(t.x)} terms, sampled max err {err:.2e}, "
+          f"sum c_k <P_k> - E {float(np.dot(t.c, got)) - e:.2e}", flush=True)
+    assert err <= 1e-12
+    assert abs(float(np.dot(t.c, got)) - e) <= 1e-9
+    plan.close()
