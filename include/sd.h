@@ -137,6 +137,13 @@ typedef struct {
        blocks per CU; 0 keeps every pass at min(tile_log2_c64, n_qubits)
        (one tile size for the whole plan, as complex128 always has). */
     int32_t tile_shrink_c64;
+    /* 1 (default): a state of fewer than 256 tiles of the size above (too
+       few to occupy the 256 CUs; each pass then waits on the latency of one
+       tile) takes, per dtype, the smallest tile of at least 2^10 that needs
+       no more passes, so that a pass spreads over more CUs.  0 keeps the
+       size above (ensembles, whose instances share the GPU, may prefer
+       it). */
+    int32_t small_state_tiles;
 } sd_plan_options;
 
 enum { SD_MODE_TILES = 0, SD_MODE_PAPER_LAYERS = 1, SD_MODE_TERMWISE = 2 };
@@ -329,7 +336,8 @@ sd_status sd_term_expectations(const sd_plan_t *p, const void *state, sd_dtype d
    candidates (the largest plan workspace among the candidates); the library
    allocates no device memory.  state: device pointer to 2^n amplitudes of
    `dtype`, used as scratch (its contents are evolved).  best: the options of
-   the fastest candidate (base with the winning size for `dtype`); seconds:
+   the fastest candidate (base with the winning size for `dtype` and
+   small_state_tiles 0: every candidate runs at its own size); seconds:
    host array of n_candidates per-step times, or NULL.  Synchronises
    `stream`.  Errors: SD_ERR_ARG, SD_ERR_RANGE (candidate out of range),
    SD_ERR_WORKSPACE (workspace too small or misaligned), SD_ERR_HIP, and

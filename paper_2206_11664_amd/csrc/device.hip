@@ -1777,6 +1777,7 @@ static sd_plan_options autotune_options(const sd_plan_options &opt, sd_dtype dty
     sd_plan_options o = opt;
     if (dtype == SD_C64) o.tile_log2_c64 = cand;
     else o.tile_log2_c128 = cand;
+    o.small_state_tiles = 0;  // (each candidate at its own size)
     if ((dtype == SD_C64 ? o.coalesce_log2_c64 : o.coalesce_log2_c128) >= cand) {
         // (the coalescing default must stay below the tile)
         if (dtype == SD_C64) o.coalesce_log2_c64 = std::min(4, cand - 1);

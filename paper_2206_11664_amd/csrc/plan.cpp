@@ -19,6 +19,7 @@ extern "C" void sd_plan_options_default(sd_plan_options *o) {
     o->mode = SD_MODE_TILES;
     o->coalesce_min_log2_c64 = 2;
     o->tile_shrink_c64 = 1;
+    o->small_state_tiles = 1;
 }
 
 namespace {
@@ -103,13 +104,32 @@ extern "C" sd_status sd_plan(const sd_hamiltonian *h, const sd_plan_options *opt
     p->mode = opt.mode;
     build_layers(*p);
 
-    sd_status st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c64,
-                                   opt.coalesce_log2_c64,
-                                   std::min(opt.coalesce_min_log2_c64, opt.coalesce_log2_c64),
-                                   &p->prog[SD_C64], opt.tile_shrink_c64 != 0);
-    if (st == SD_OK)
-        st = compile_program(p->n, p->terms, p->groups, opt.tile_log2_c128,
-                             opt.coalesce_log2_c128, opt.coalesce_log2_c128, &p->prog[SD_C128], false);
+    auto compile = [&](int d, int D, Program *out) {
+        return d == SD_C64 ? compile_program(p->n, p->terms, p->groups, D, opt.coalesce_log2_c64,
+                                             std::min(opt.coalesce_min_log2_c64, opt.coalesce_log2_c64),
+                                             out, opt.tile_shrink_c64 != 0)
+                           : compile_program(p->n, p->terms, p->groups, D, opt.coalesce_log2_c128,
+                                             opt.coalesce_log2_c128, out, false);
+    };
+    sd_status st = SD_OK;
+    for (int d = 0; d < 2 && st == SD_OK; ++d) {
+        const int D = d == SD_C64 ? opt.tile_log2_c64 : opt.tile_log2_c128;
+        const int coal = d == SD_C64 ? opt.coalesce_log2_c64 : opt.coalesce_log2_c128;
+        st = compile(d, D, &p->prog[d]);
+        // A state of fewer than kLatencyTiles tiles leaves most CUs idle and
+        // each pass waits on the latency of one tile: take the smallest tile
+        // of at least 2^kTileMinLog2Fast that needs no more passes.
+        if (st != SD_OK || !opt.small_state_tiles || p->n - std::min(D, p->n) >= kLatencyTilesLog2) continue;
+        for (int Dt = kTileMinLog2Fast; Dt < std::min(D, p->n); ++Dt) {
+            if (coal >= Dt) continue;
+            Program alt;
+            if (compile(d, Dt, &alt) != SD_OK) continue;
+            if (alt.passes.size() <= p->prog[d].passes.size()) {
+                p->prog[d] = std::move(alt);
+                break;
+            }
+        }
+    }
     if (st != SD_OK) {
         delete p;
         return st;

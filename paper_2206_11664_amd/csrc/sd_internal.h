@@ -109,6 +109,8 @@ SynthResult synthesize(int n, const std::vector<Row> &terms, const SynthOptions 
 constexpr int kMaxTileLog2 = 13;   // on-chip tile limit (LDS, FP64 staging)
 constexpr int kMinTileLog2 = 6;
 constexpr int kRegBits = 4;        // tile coordinates held in registers per round
+constexpr int kTileMinLog2Fast = 10;   // smallest tile of the register-round kernel
+constexpr int kLatencyTilesLog2 = 8;   // below 2^8 tiles a pass leaves CUs idle (256 CUs)
 constexpr int kXBits = 2;          // coordinates exchanged with lane bits 4, 5
 constexpr int kChunkBits = kRegBits + kXBits;   // span coordinates per round
 

@@ -48,7 +48,8 @@ class sd_plan_options(ctypes.Structure):
     _fields_ = [("skip_rule", ctypes.c_int32), ("tile_log2_c64", ctypes.c_int32),
                 ("tile_log2_c128", ctypes.c_int32), ("coalesce_log2_c64", ctypes.c_int32),
                 ("coalesce_log2_c128", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("coalesce_min_log2_c64", ctypes.c_int32), ("tile_shrink_c64", ctypes.c_int32)]
+                ("coalesce_min_log2_c64", ctypes.c_int32), ("tile_shrink_c64", ctypes.c_int32),
+                ("small_state_tiles", ctypes.c_int32)]
 
 
 class sd_plan_info(ctypes.Structure):

@@ -31,6 +31,8 @@ def gpu_evolve(m, psi0, dtype, dt, steps, order, opts=None, plan=None):
     print(f"[gpu] {m.name} n={m.n} dtype={dtype} steps={steps} order={order}", flush=True)
     if plan is None:
         o = sd.sd_plan_options_default()
+        if any(k.startswith("tile_log2") for k in (opts or {})):
+            o.small_state_tiles = 0  # (a test asking for a tile size gets that size)
         for k, v in (opts or {}).items():
             setattr(o, k, v)
         plan = sd.Plan(m.n, m.paulis, m.coeffs, o).bind()

@@ -24,6 +24,8 @@ def _libs(oracle_lib):
 
 def plan_for(n, paulis, coeffs, **opt):
     o = sd.sd_plan_options_default()
+    if any(k.startswith("tile_log2") for k in opt):
+        o.small_state_tiles = 0  # (a test asking for a tile size gets that size)
     for k, v in opt.items():
         setattr(o, k, v)
     h = sd.sd_hamiltonian_create(n, paulis, coeffs)
@@ -571,3 +573,40 @@ def test_jw_generator_rejects_impossible_totals():
     with pytest.raises(ValueError):
         workloads.jw_fermionic(n=12)
     assert len(workloads.jw_fermionic(n=12, total=2000).paulis) == 2000
+
+
+def _pass_tiles(p, dtype):
+    return [sd.sd_plan_export_pass(p, dtype, i)["tile_log2"] for i in range(sd.sd_plan_pass_count(p, dtype))]
+
+
+def test_small_state_tiles():
+    # a state of fewer than 256 tiles of the requested size takes the
+    # smallest tile (>= 2^10) that needs no more passes; a large state keeps
+    # the requested size; the option off keeps it too
+    m = workloads.tfim_fully_connected(14)
+    for dtype in (sd.SD_C64, sd.SD_C128):
+        h, p = plan_for(m.n, m.paulis, m.coeffs)
+        h0, p0 = plan_for(m.n, m.paulis, m.coeffs, small_state_tiles=0)
+        t, t0 = _pass_tiles(p, dtype), _pass_tiles(p0, dtype)
+        assert len(t) == len(t0)
+        assert max(t) < max(t0) and min(t) >= 10
+        # the smallest such size: one below it needs more passes
+        if max(t) > 10:
+            h1, p1 = plan_for(m.n, m.paulis, m.coeffs, small_state_tiles=0,
+                              **{("tile_log2_c64" if dtype == sd.SD_C64 else "tile_log2_c128"): max(t) - 1})
+            assert len(_pass_tiles(p1, dtype)) > len(t)
+            sd.sd_plan_destroy(p1)
+            sd.sd_hamiltonian_destroy(h1)
+        for q in (p, p0):
+            sd.sd_plan_destroy(q)
+        for g in (h, h0):
+            sd.sd_hamiltonian_destroy(g)
+    big = workloads.random_klocal(n=22, m=300, seed=3, init_seed=2)
+    h, p = plan_for(big.n, big.paulis, big.coeffs)
+    h0, p0 = plan_for(big.n, big.paulis, big.coeffs, small_state_tiles=0)
+    for dtype in (sd.SD_C64, sd.SD_C128):
+        assert _pass_tiles(p, dtype) == _pass_tiles(p0, dtype)
+    for q in (p, p0):
+        sd.sd_plan_destroy(q)
+    for g in (h, h0):
+        sd.sd_hamiltonian_destroy(g)
