@@ -212,7 +212,8 @@ def ensemble_experiment(args, torch, workloads, sd):
     sd_ensemble_evolve (one multi-instance tile launch per pass level and
     tile size, one step replayed as a HIP graph).  Timed: --steps steps after
     --warmup, for complex64 and complex128; beside it the same instances
-    evolved one after another with sd_evolve.  Algorithmic bytes: every group
+    evolved one after another with sd_evolve.  The tile size is autotuned on
+    the whole ensemble first (--no-autotune: 2^13).  Algorithmic bytes: every group
     application of every instance reads and writes its state once,
     2 * 2^n_i * B bytes (4 applications per second-order step of the three
     XXZ groups, the G_0 halves of consecutive steps joined); the bytes of all
@@ -223,12 +224,6 @@ def ensemble_experiment(args, torch, workloads, sd):
     stream = torch.cuda.current_stream()
     models = workloads.xxz_ensemble()
     dt, order = models[0].dt, models[0].order
-    log(f"ensemble: planning {len(models)} instances")
-    t0 = time.time()
-    o = sd.sd_plan_options_default()
-    o.tile_shrink_c64 = args.tile_shrink
-    plans = [sd.Plan(m.n, m.paulis, m.coeffs, o).bind("cuda") for m in models]
-    plan_s = time.time() - t0
     amps = sum(1 << m.n for m in models)
 
     def timed(fn, steps):
@@ -240,6 +235,42 @@ def ensemble_experiment(args, torch, workloads, sd):
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
+
+    o = sd.sd_plan_options_default()
+    o.tile_shrink_c64 = args.tile_shrink
+    tune = {}
+    # The tile size (LDS block) on this GPU: every candidate maximum tile size
+    # timed on the whole ensemble (10 steps after 2), per precision; complex64
+    # keeps only sizes that need no more passes than 2^13 (each pass rounds
+    # every amplitude once).  Ties within 1% go to the larger tile.
+    for name, dtype, tdt, attr in (() if args.no_autotune else
+                                   (("c64", sd.SD_C64, torch.complex64, "tile_log2_c64"),
+                                    ("c128", sd.SD_C128, torch.complex128, "tile_log2_c128"))):
+        secs, npass = {}, {}
+        for c in (12, 13):
+            oc = sd.sd_plan_options_default()
+            oc.tile_shrink_c64 = args.tile_shrink
+            setattr(oc, attr, c)
+            pl = [sd.Plan(m.n, m.paulis, m.coeffs, oc).bind("cuda") for m in models]
+            npass[c] = sum(passes_per_step(p, dtype, order) for p in pl)
+            ens = sd.sd_ensemble_create([p.p for p in pl], dtype)
+            ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+            sd.sd_ensemble_bind_workspace(ens, ws)
+            sts = [torch.from_numpy(m.initial_state()).to(tdt).cuda() for m in models]
+            sd.sd_ensemble_evolve(ens, sts, dt, 2, order)
+            secs[c] = timed(lambda k: sd.sd_ensemble_evolve(ens, sts, dt, k, order), 10) / 10
+            sd.sd_ensemble_destroy(ens)
+            del ws, sts, pl
+        ok = [c for c in secs if dtype != sd.SD_C64 or npass[c] <= npass[13]]
+        chosen = max(c for c in ok if secs[c] <= 1.01 * min(secs[x] for x in ok))
+        setattr(o, attr, chosen)
+        tune[name] = {"step_ms": {str(c): round(1e3 * t, 3) for c, t in secs.items()},
+                      "instance_passes_per_step": {str(c): v for c, v in npass.items()}, "chosen": chosen}
+        log(f"ensemble autotune {name}: {tune[name]}")
+    log(f"ensemble: planning {len(models)} instances")
+    t0 = time.time()
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs, o).bind("cuda") for m in models]
+    plan_s = time.time() - t0
 
     res = {}
     finals = {}
@@ -295,7 +326,8 @@ def ensemble_experiment(args, torch, workloads, sd):
            "config": {"workload": "xxz_open_ensemble_256", "instances": len(models),
                       "n_range": [min(m.n for m in models), max(m.n for m in models)],
                       "amplitudes": amps, "order": order, "dt": dt, "seed": 4},
-           "plan_seconds": round(plan_s, 2), "tile_shrink_c64": args.tile_shrink, **res,
+           "plan_seconds": round(plan_s, 2), "tile_shrink_c64": args.tile_shrink,
+           "tile_log2": {"c64": int(o.tile_log2_c64), "c128": int(o.tile_log2_c128)}, "autotune": tune, **res,
            "accuracy_c64_vs_c128": {"steps": args.warmup + args.steps,
                                     "mean_1_minus_F": float(1.0 - np.mean(fids)),
                                     "max_1_minus_F": float(1.0 - np.min(fids))}}
