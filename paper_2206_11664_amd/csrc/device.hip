@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "device_types.h"
@@ -391,6 +392,32 @@ __device__ __forceinline__ void cis_scaled(double x, CP kc, CP ks, double &c, do
     }
     c = pc;
     s = ps * x;
+}
+
+// Sum of v over the 64 lanes of a wave (every lane active), the same value
+// in every lane: within each 16-lane row by DPP moves (lane i ^ 1, lane
+// i ^ 2, then the mirrored lane of its half-row and of its row: after each
+// step every lane holds the sum over its pair, quad, half-row, row), then
+// the four row sums read out of lanes 0, 16, 32, 48 and added in that order.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    auto dpp = [](double x, auto ctrl) {
+        const uint64_t u = (uint64_t)__double_as_longlong(x);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, decltype(ctrl)::value, 0xF, 0xF, false);
+        const uint32_t hi =
+            (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), decltype(ctrl)::value, 0xF, 0xF, false);
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    };
+    v += dpp(v, std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
+    v += dpp(v, std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
+    v += dpp(v, std::integral_constant<int, 0x141>{});  // row_half_mirror
+    v += dpp(v, std::integral_constant<int, 0x140>{});  // row_mirror
+    auto row = [&](int l) {
+        const uint64_t u = (uint64_t)__double_as_longlong(v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    };
+    return ((row(0) + row(16)) + row(32)) + row(48);
 }
 
 // butterflies on register bit L.  Forward: (a, c) -> (a + w c, a - w c) with
@@ -986,7 +1013,7 @@ __device__ __forceinline__ void tile_pass(T *__restrict__ state, PDP __restrict_
                         const uint32_t z = (uint32_t)__double_as_longlong(rec.y);
                         const uint64_t flip = (uint64_t)__popc(z & sgnb) << 63;
                         double v = __longlong_as_double((long long)((uint64_t)__double_as_longlong(rec.x) ^ flip)) * W[w];
-                        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                        v = wave_sum_f64(v);
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             if ((k >> 6) == q && lane == (k & 63)) acc[q] += v;
