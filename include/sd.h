@@ -134,8 +134,10 @@ typedef struct {
     int32_t coalesce_min_log2_c64;
     /* complex64: 1 (default) gives each pass the smallest tile (at least
        2^10) that holds its sub-group, so that small passes run several
-       blocks per CU; 0 keeps every pass at min(tile_log2_c64, n_qubits)
-       (one tile size for the whole plan, as complex128 always has). */
+       blocks per CU, and splits each group for tiles one or two
+       coordinates smaller where that needs no more passes; 0 keeps every
+       pass at min(tile_log2_c64, n_qubits) (one tile size for the whole
+       plan, as complex128 always has). */
     int32_t tile_shrink_c64;
     /* 1 (default): a state of fewer than 256 tiles of the size above (too
        few to occupy the 256 CUs; each pass then waits on the latency of one
