@@ -398,6 +398,7 @@ def config_experiment(args, torch, workloads, sd):
     # accuracy: the same steps from the same state in both precisions
     a = state(torch.complex64)
     b = state(torch.complex128)
+    e0 = plan.expectation(b)
     done = 0
     while done < acc_steps:
         k = min(100, acc_steps - done)
@@ -416,6 +417,7 @@ def config_experiment(args, torch, workloads, sd):
         aa = a[i:i + (1 << 28)].to(torch.complex128)
         ov += complex(torch.vdot(b[i:i + (1 << 28)], aa))
     fid = abs(ov) ** 2 / (na * nb)
+    ea, eb = plan.expectation(a), plan.expectation(b)
     out = {"experiment": args.experiment,
            "metric": "Trotter steps/s (grouped), c64 amplitudes + FP64 phase vs c128",
            "unit": "steps/s",
@@ -426,6 +428,8 @@ def config_experiment(args, torch, workloads, sd):
            "group_applications_per_step": apps, **res,
            "c64_over_c128": round(res["c64"]["steps_per_s"] / res["c128"]["steps_per_s"], 3),
            "accuracy_c64_vs_c128": {"steps": acc_steps, "l2": l2sq ** 0.5, "max_abs": mx,
+                                    "energy_initial": e0, "energy_drift_c64": ea - e0,
+                                    "energy_drift_c128": eb - e0,
                                     "1_minus_fidelity": 1.0 - fid, "norm_drift_c64": na - 1.0,
                                     "norm_drift_c128": nb - 1.0}}
     print(json.dumps(out), flush=True)
