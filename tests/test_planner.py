@@ -610,3 +610,25 @@ def test_small_state_tiles():
         sd.sd_plan_destroy(q)
     for g in (h, h0):
         sd.sd_hamiltonian_destroy(g)
+
+
+def test_shrink_never_adds_passes():
+    # complex64 tile shrinking (smallest tile per pass, and each group split
+    # again for tiles one or two coordinates smaller while that needs no more
+    # passes) never needs more passes than one tile size for the whole plan;
+    # at n = 28 the benchmark keeps its 139 passes and moves most of them off
+    # 2^13 tiles
+    cases = [(workloads.random_klocal(28), 139), (workloads.xxz_chain(26), None),
+             (workloads.random_klocal(n=20, m=600, seed=7, init_seed=2), None),
+             (workloads.jw_fermionic(n=16, total=900), None)]
+    for m, want in cases:
+        h, p = plan_for(m.n, m.paulis, m.coeffs)
+        h0, p0 = plan_for(m.n, m.paulis, m.coeffs, tile_shrink_c64=0)
+        t, t0 = _pass_tiles(p, sd.SD_C64), _pass_tiles(p0, sd.SD_C64)
+        assert len(t) <= len(t0), (m.name, len(t), len(t0))
+        if want is not None:
+            assert len(t) == want and sum(1 for d in t if d < 13) > len(t) // 2, (len(t), t.count(13))
+        for q in (p, p0):
+            sd.sd_plan_destroy(q)
+        for g in (h, h0):
+            sd.sd_hamiltonian_destroy(g)
