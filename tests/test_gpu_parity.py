@@ -303,6 +303,41 @@ def test_ensemble_of_small_instances_only(dtype):
     sd.sd_ensemble_destroy(ens)
 
 
+def test_ensemble_with_a_state_above_4gib():
+    # complex128 n = 29 (8 GiB: the multi-instance kernel's 32-bit offsets do
+    # not reach it, so it takes single-instance pass launches inside the step
+    # graphs) beside an n = 12 instance: both equal their own sd_evolve bit
+    # for bit, on a second call that replays the graphs too
+    big = workloads.random_klocal(n=29, m=60, seed=12, init_seed=13)
+    small = workloads.random_klocal(n=12, m=80, seed=14, init_seed=15)
+    plans = [sd.Plan(m.n, m.paulis, m.coeffs).bind() for m in (big, small)]
+    print(f"[gpu] ensemble with n=29 complex128: passes {[p.info.passes_c128 for p in plans]}", flush=True)
+    ens = sd.sd_ensemble_create([p.p for p in plans], sd.SD_C128)
+    ws = torch.empty(sd.sd_ensemble_workspace_bytes(ens), dtype=torch.uint8, device="cuda")
+    sd.sd_ensemble_bind_workspace(ens, ws)
+    states = [torch.zeros(1 << 29, dtype=torch.complex128, device="cuda"),
+              torch.from_numpy(workloads.random_state(12, 16)).cuda()]
+    states[0][5] = 0.6
+    states[0][(1 << 29) - 3] = 0.8
+    singles = [s.clone() for s in states]
+    for _ in range(2):
+        sd.sd_ensemble_evolve(ens, states, 0.05, 2, 2)
+    for p, st in zip(plans, singles):
+        for _ in range(2):
+            p.evolve(st, 0.05, 2, 2)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(states, singles)):
+        assert torch.equal(a, b), i
+    n2 = sd.sd_norm2(states[0], 29)
+    print(f"[gpu] ensemble with n=29: bit-identical to sd_evolve, norm drift {n2 - 1:.2e}", flush=True)
+    assert abs(n2 - 1) <= 1e-12
+    sd.sd_ensemble_destroy(ens)
+    del states, singles, ws
+    for p in plans:
+        p.close()
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("shrink", [1, 0])
 def test_ensemble_after_plan_rebind(shrink):
     # a member plan rebound to a new workspace (the old one released) between
