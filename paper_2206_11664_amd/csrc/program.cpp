@@ -22,6 +22,9 @@
 // A group whose tile would exceed the on-chip limit is split into commuting
 // sub-groups (any split is exact: the terms commute), each with its own tile.
 #include <algorithm>
+#include <atomic>
+#include <string>
+#include <thread>
 #include <functional>
 #include <unordered_map>
 #include <array>
@@ -841,6 +844,7 @@ sd_status build_pass(int n, const std::vector<Term> &T, int32_t group,
 // Splits of a group into sub-groups are compared by the sum over their passes.
 constexpr int kShrinkMaxTerms = 32;  // passes with more Lambda terms keep the full tile
 constexpr int kShrinkMinCap = 11;    // smallest tile a group split is tried for (shrink)
+constexpr int kPlannerThreads = 16;  // host threads compiling groups
 
 // Extra modelled time per pass of a tile with one or two fewer contiguous low
 // bits than the 128-byte line (fitted: 64-byte runs cost about 130, 32-byte
@@ -862,7 +866,16 @@ sd_status compile_program(int n, const std::vector<Term> &T,
     P.group_first.assign(1, 0);
     const int cc = std::min(c, n);
     const int Dcap = std::min(D_max, n);
-    for (size_t g = 0; g < groups.size(); ++g) {
+    // The groups are compiled independently (their own seeded searches), on
+    // a few host threads; the passes are then joined in group order, so the
+    // program does not depend on the thread count.
+    struct GroupOut {
+        sd_status st = SD_OK;
+        std::string err;
+        std::vector<PassHost> passes;
+    };
+    std::vector<GroupOut> outs(groups.size());
+    auto compile_group = [&](const size_t g) {
         // Split into sub-groups whose tile space (X span + low bits) fits.
         // Sub-groups are grown one at a time: first every remaining term whose
         // X part already lies in the span joins (no growth), then the term
@@ -1118,7 +1131,8 @@ sd_status compile_program(int n, const std::vector<Term> &T,
         // then take tiles of 2^12 or 2^11, which run two or four blocks per CU
         // whose barriers do not stall each other (n = 28: 139 passes either
         // way, 1.8% less time per step).
-        if (shrink) {
+        // (a group of one pass already has its smallest tile)
+        if (shrink && best_split.size() > 1) {
             for (int cap = Dcap - 1; cap >= std::max(kShrinkMinCap, cg + 1) && cap >= Dcap - 2; --cap) {
                 auto r3 = split_group(cg, cap);
                 if (r3.first.size() > best_split.size()) break;
@@ -1141,9 +1155,31 @@ sd_status compile_program(int n, const std::vector<Term> &T,
                 Dt = std::min(Dcap, std::max(sp.dim(), 2 * kRegBits + kXBits));
             }
             sd_status st = build_pass(n, T, (int32_t)g, s, Dt, cg, &ps);
-            if (st != SD_OK) return st;
-            P.passes.push_back(std::move(ps));
+            if (st != SD_OK) {
+                // (the message is in this thread's last error)
+                outs[g].st = st;
+                outs[g].err = sd_last_error();
+                return;
+            }
+            outs[g].passes.push_back(std::move(ps));
         }
+    };
+    const size_t nthreads = std::min<size_t>(
+        {groups.size(), (size_t)kPlannerThreads, (size_t)std::max(1u, std::thread::hardware_concurrency())});
+    if (nthreads <= 1) {
+        for (size_t g = 0; g < groups.size(); ++g) compile_group(g);
+    } else {
+        std::atomic<size_t> next{0};
+        std::vector<std::thread> pool;
+        for (size_t t = 0; t < nthreads; ++t)
+            pool.emplace_back([&]() {
+                for (size_t g = next++; g < groups.size(); g = next++) compile_group(g);
+            });
+        for (auto &th : pool) th.join();
+    }
+    for (size_t g = 0; g < groups.size(); ++g) {
+        if (outs[g].st != SD_OK) return fail(outs[g].st, outs[g].err);
+        for (auto &ps : outs[g].passes) P.passes.push_back(std::move(ps));
         P.group_first.push_back((int32_t)P.passes.size());
     }
     return SD_OK;
